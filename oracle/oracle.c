@@ -1,0 +1,312 @@
+/*
+ * CPU ORACLE for the Hough-transform track finder -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously-correct C.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this file's library; the product
+ * path never does.  It shares no code, header, table or helper with the GPU
+ * library: it builds its own tables from the definitions below.
+ *
+ * What is computed (Section 3 of the paper, "Hough Transform Algorithm"):
+ *   step 1 -- every hit adds a vote to each parameter-space cell whose track
+ *             would contain it (the two-variable curvature/azimuth grid);
+ *   step 2 -- cells with many votes are candidates; finding them is a
+ *             local-maximum search over the grid.
+ * The Discussion section describes step 1 as the indirect update A[B[i]] += 1;
+ * orc_vote_count() is that counting form.  orc_vote_mask() is the form the
+ * tracker uses: a cell holds the OR of the layer bits of its voters, and the
+ * "number of votes" of a cell is the popcount of that mask.
+ *
+ * Readings of points the paper leaves open (all listed in the design notes):
+ *   - track model: circle of signed curvature rho = 0.299792458e-3 * B * q/pT
+ *     [1/mm], perigee (d0, phi0), B along +z, q/pT > 0 bends clockwise; a hit
+ *     at radius r lies at phi = phi0 + asin(arg) with
+ *     arg = (d0 - rho (r^2 + d0^2) / 2) / (r (1 - rho d0));
+ *   - bins: q/pT, d0 and cot(theta) at bin centres; phi0 bin p covers the turn
+ *     fractions [p/Nphi, (p+1)/Nphi); angles are uint32 turn fractions;
+ *   - rounding: llround (half away from zero) for tables, floor for z0 bins;
+ *   - local maximum: popcount >= threshold and >= every neighbour in the
+ *     3x3 (q/pT, phi0) window (3x3x3 with d0); phi0 wraps, the others do not;
+ *   - rz refinement: members of a candidate are the hits that voted into its
+ *     exact cell; each member votes once per cot(theta) bin for
+ *     z0 = z - cot * s(r), s the transverse arc length; result is the argmax
+ *     with ties to the smallest cot bin, then the smallest z0 bin.
+ *
+ * Every function is pinned by the CPU test-suite (brute force, closed forms,
+ * invariants, bin-centre tracks); none is "parity unpinned".
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    uint32_t n_layers;
+    double   layer_r_mm[16];
+    double   b_tesla;
+    uint32_t n_qpt;
+    double   qpt_lo, qpt_hi;
+    uint32_t n_phi;
+    uint32_t n_d0;
+    double   d0_lo_mm, d0_hi_mm;
+    uint32_t threshold;
+    uint32_t n_z0;
+    int32_t  z0_lo_um, z0_hi_um;
+    uint32_t n_cot;
+    double   cot_lo, cot_hi;
+    uint32_t rz_max_candidates;
+} orc_spec;
+
+/* ---- spec ------------------------------------------------------------- */
+
+static int is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+static uint32_t log2u(uint32_t v) { uint32_t s = 0; while ((1u << s) < v) s++; return s; }
+
+int orc_check_spec(const orc_spec *g)
+{
+    if (g->n_layers < 1 || g->n_layers > 16) return -1;
+    for (uint32_t l = 0; l < g->n_layers; l++) {
+        if (!(g->layer_r_mm[l] > 0.0)) return -1;
+        if (l && !(g->layer_r_mm[l] > g->layer_r_mm[l - 1])) return -1;
+    }
+    if (!is_pow2(g->n_phi) || g->n_phi < 2 || g->n_phi > 65536) return -1;
+    if (g->n_qpt < 1 || g->n_d0 < 1) return -1;
+    if ((uint64_t)g->n_d0 * g->n_qpt * g->n_phi > 0xFFFFFFFFull) return -1;
+    if (g->n_z0) {
+        if (g->n_d0 != 1 || g->n_cot < 1 || g->n_cot > 65535 || g->n_z0 > 65535) return -1;
+        if (!((int64_t)g->z0_hi_um > (int64_t)g->z0_lo_um)) return -1;
+    }
+    return 0;
+}
+
+/* Bin centres (O1). */
+static double kappa_of(const orc_spec *g, uint32_t k)
+{
+    return g->qpt_lo + (k + 0.5) * ((g->qpt_hi - g->qpt_lo) / g->n_qpt);
+}
+static double d0_of(const orc_spec *g, uint32_t d)
+{
+    if (g->n_d0 == 1) return 0.0;
+    return g->d0_lo_mm + (d + 0.5) * ((g->d0_hi_mm - g->d0_lo_mm) / g->n_d0);
+}
+static double cot_of(const orc_spec *g, uint32_t j)
+{
+    return g->cot_lo + (j + 0.5) * ((g->cot_hi - g->cot_lo) / g->n_cot);
+}
+
+/* ---- tables (O2, O5) --------------------------------------------------- */
+
+/* O[l][d][k]: uint32 turn fraction of (phi_hit - phi0) for the bin-centre
+ * track (kappa_k, d0_d) at radius r_l; V = 0 where the layer is unreachable. */
+void orc_offsets(const orc_spec *g, uint32_t *O, uint8_t *V)
+{
+    for (uint32_t l = 0; l < g->n_layers; l++)
+        for (uint32_t d = 0; d < g->n_d0; d++)
+            for (uint32_t k = 0; k < g->n_qpt; k++) {
+                double r = g->layer_r_mm[l];
+                double d0 = d0_of(g, d);
+                double rho = (0.299792458e-3 * g->b_tesla) * kappa_of(g, k);
+                double den = r * (1.0 - rho * d0);
+                double arg = (d0 - rho * (r * r + d0 * d0) * 0.5) / den;
+                int ok = (1.0 - rho * d0) > 0.0 && fabs(arg) <= 1.0;
+                size_t i = ((size_t)l * g->n_d0 + d) * g->n_qpt + k;
+                V[i] = (uint8_t)ok;
+                O[i] = ok ? (uint32_t)(int64_t)llround(asin(arg) / (2.0 * M_PI) * 4294967296.0) : 0u;
+            }
+}
+
+/* Z[k][l][j]: cot_j times the transverse arc length to radius r_l of the
+ * prompt bin-centre track kappa_k, in integer micrometres. */
+void orc_zshift(const orc_spec *g, int32_t *Z)
+{
+    for (uint32_t k = 0; k < g->n_qpt; k++)
+        for (uint32_t l = 0; l < g->n_layers; l++)
+            for (uint32_t j = 0; j < g->n_cot; j++) {
+                double r = g->layer_r_mm[l];
+                double rho = (0.299792458e-3 * g->b_tesla) * kappa_of(g, k);
+                double s = (rho == 0.0) ? r : (2.0 / rho) * asin(rho * r * 0.5);
+                Z[((size_t)k * g->n_layers + l) * g->n_cot + j] =
+                    (int32_t)llround(cot_of(g, j) * s * 1000.0);
+            }
+}
+
+/* ---- step 1: voting (O3, O3') ----------------------------------------- */
+
+/* A[d][k][p] |= 1 << layer for every hit and every reachable row. */
+void orc_vote_mask(const orc_spec *g, const uint32_t *O, const uint8_t *V,
+                   uint64_t n_hits, const uint8_t *layer, const uint32_t *phi,
+                   uint16_t *A)
+{
+    uint32_t s = 32 - log2u(g->n_phi);
+    size_t cells = (size_t)g->n_d0 * g->n_qpt * g->n_phi;
+    memset(A, 0, cells * sizeof(uint16_t));
+    for (uint64_t h = 0; h < n_hits; h++) {
+        uint32_t l = layer[h];
+        if (l >= g->n_layers) continue;
+        for (uint32_t d = 0; d < g->n_d0; d++)
+            for (uint32_t k = 0; k < g->n_qpt; k++) {
+                size_t t = ((size_t)l * g->n_d0 + d) * g->n_qpt + k;
+                if (!V[t]) continue;
+                uint32_t p = (uint32_t)(phi[h] - O[t]) >> s;
+                A[((size_t)d * g->n_qpt + k) * g->n_phi + p] |= (uint16_t)(1u << l);
+            }
+    }
+}
+
+/* The paper's counting form: C[d][k][p] += 1. */
+void orc_vote_count(const orc_spec *g, const uint32_t *O, const uint8_t *V,
+                    uint64_t n_hits, const uint8_t *layer, const uint32_t *phi,
+                    uint32_t *C)
+{
+    uint32_t s = 32 - log2u(g->n_phi);
+    size_t cells = (size_t)g->n_d0 * g->n_qpt * g->n_phi;
+    memset(C, 0, cells * sizeof(uint32_t));
+    for (uint64_t h = 0; h < n_hits; h++) {
+        uint32_t l = layer[h];
+        if (l >= g->n_layers) continue;
+        for (uint32_t d = 0; d < g->n_d0; d++)
+            for (uint32_t k = 0; k < g->n_qpt; k++) {
+                size_t t = ((size_t)l * g->n_d0 + d) * g->n_qpt + k;
+                if (!V[t]) continue;
+                uint32_t p = (uint32_t)(phi[h] - O[t]) >> s;
+                C[((size_t)d * g->n_qpt + k) * g->n_phi + p] += 1;
+            }
+    }
+}
+
+/* ---- step 2: local maxima (O4) ---------------------------------------- */
+
+static int popc16(uint16_t v) { return __builtin_popcount((unsigned)v); }
+
+/* Peaks in ascending cell order; writes at most cap records, returns the
+ * true number of peaks. */
+uint64_t orc_peaks(const orc_spec *g, const uint16_t *A,
+                   uint32_t *cell, uint16_t *mask, uint16_t *pc, uint64_t cap)
+{
+    uint64_t n = 0;
+    int nd = (int)g->n_d0, nk = (int)g->n_qpt, np = (int)g->n_phi;
+    for (int d = 0; d < nd; d++)
+        for (int k = 0; k < nk; k++)
+            for (int p = 0; p < np; p++) {
+                size_t c = ((size_t)d * nk + k) * np + p;
+                int v = popc16(A[c]);
+                if (v < (int)g->threshold) continue;
+                int is_max = 1;
+                for (int dd = -1; dd <= 1 && is_max; dd++) {
+                    if (nd == 1 && dd != 0) continue;          /* 2D grid: no d0 axis */
+                    int d2 = d + dd;
+                    if (d2 < 0 || d2 >= nd) continue;
+                    for (int dk = -1; dk <= 1 && is_max; dk++) {
+                        int k2 = k + dk;
+                        if (k2 < 0 || k2 >= nk) continue;
+                        for (int dp = -1; dp <= 1; dp++) {
+                            if (dd == 0 && dk == 0 && dp == 0) continue;
+                            int p2 = ((p + dp) % np + np) % np;
+                            if (popc16(A[((size_t)d2 * nk + k2) * np + p2]) > v) { is_max = 0; break; }
+                        }
+                    }
+                }
+                if (!is_max) continue;
+                if (n < cap) {
+                    cell[n] = (uint32_t)c;
+                    mask[n] = A[c];
+                    pc[n] = (uint16_t)v;
+                }
+                n++;
+            }
+    return n;
+}
+
+/* ---- rz refinement (O5) ----------------------------------------------- */
+
+static int64_t floor_div64(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b) != 0 && ((a < 0) != (b < 0))) q--;
+    return q;
+}
+
+/* Candidate order: all peaks in list order, or the first rz_max_candidates
+ * peaks ordered by (popcount descending, cell ascending). */
+uint64_t orc_rz_candidates(const orc_spec *g, uint64_t n_peaks, const uint16_t *pc,
+                           uint32_t *cand)
+{
+    uint64_t cap = g->rz_max_candidates;
+    if (cap == 0) {
+        for (uint64_t i = 0; i < n_peaks; i++) cand[i] = (uint32_t)i;
+        return n_peaks;
+    }
+    uint64_t n = 0;
+    for (int v = 16; v >= 0 && n < cap; v--)
+        for (uint64_t i = 0; i < n_peaks && n < cap; i++)
+            if (pc[i] == v) cand[n++] = (uint32_t)i;
+    return n;
+}
+
+/* For each candidate: member hits, then the (cot, z0) vote and its argmax.
+ * Returns the number of records (= number of candidates). */
+uint64_t orc_rz(const orc_spec *g, const uint32_t *O, const uint8_t *V, const int32_t *Z,
+                uint64_t n_hits, const uint8_t *layer, const uint32_t *phi, const int32_t *z,
+                uint64_t n_peaks, const uint32_t *cell, const uint16_t *pc,
+                uint32_t *out_peak, uint16_t *out_cot, uint16_t *out_z0,
+                uint32_t *out_count, uint32_t *out_nmem)
+{
+    uint32_t s = 32 - log2u(g->n_phi);
+    uint32_t *cand = (uint32_t *)malloc((n_peaks + 1) * sizeof(uint32_t));
+    uint64_t n_cand = orc_rz_candidates(g, n_peaks, pc, cand);
+    uint64_t *mem = (uint64_t *)malloc((n_hits + 1) * sizeof(uint64_t));
+    int32_t *hist = (int32_t *)calloc(g->n_z0, sizeof(int32_t));
+    int64_t *bins = (int64_t *)malloc((n_hits + 1) * sizeof(int64_t));
+    int64_t span = (int64_t)g->z0_hi_um - (int64_t)g->z0_lo_um;
+
+    for (uint64_t c = 0; c < n_cand; c++) {
+        uint32_t pk = cand[c];
+        uint32_t k = (cell[pk] / g->n_phi) % g->n_qpt;     /* n_d0 == 1 here */
+        uint32_t p = cell[pk] % g->n_phi;
+        /* members: hits that voted into this exact cell */
+        uint64_t nm = 0;
+        for (uint64_t h = 0; h < n_hits; h++) {
+            uint32_t l = layer[h];
+            if (l >= g->n_layers) continue;
+            size_t t = (size_t)l * g->n_qpt + k;
+            if (!V[t]) continue;
+            if (((uint32_t)(phi[h] - O[t]) >> s) == p) mem[nm++] = h;
+        }
+        /* dense argmax over (j, b) of R[j][b], evaluated one cot row at a time */
+        int64_t best = 0; uint32_t best_j = 0, best_b = 0;
+        for (uint32_t j = 0; j < g->n_cot; j++) {
+            for (uint64_t m = 0; m < nm; m++) {
+                uint64_t h = mem[m];
+                int64_t z0 = (int64_t)z[h] - (int64_t)Z[((size_t)k * g->n_layers + layer[h]) * g->n_cot + j];
+                int64_t b = floor_div64((z0 - (int64_t)g->z0_lo_um) * (int64_t)g->n_z0, span);
+                bins[m] = b;
+                if (b >= 0 && b < (int64_t)g->n_z0) hist[b]++;
+            }
+            /* the row's maximum, smallest bin among ties */
+            int64_t row_best = 0; int64_t row_b = 0;
+            for (uint64_t m = 0; m < nm; m++) {
+                int64_t b = bins[m];
+                if (b < 0 || b >= (int64_t)g->n_z0) continue;
+                if (hist[b] > row_best || (hist[b] == row_best && b < row_b)) {
+                    row_best = hist[b]; row_b = b;
+                }
+            }
+            for (uint64_t m = 0; m < nm; m++) {
+                int64_t b = bins[m];
+                if (b >= 0 && b < (int64_t)g->n_z0) hist[b] = 0;
+            }
+            if (row_best > best) { best = row_best; best_j = j; best_b = (uint32_t)row_b; }
+        }
+        out_peak[c] = pk;
+        out_cot[c] = (uint16_t)best_j;
+        out_z0[c] = (uint16_t)best_b;
+        out_count[c] = (uint32_t)best;
+        out_nmem[c] = (uint32_t)nm;
+    }
+    free(cand); free(mem); free(hist); free(bins);
+    return n_cand;
+}
