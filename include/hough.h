@@ -1,0 +1,243 @@
+/*
+ * hough.h -- C ABI of the MI355X (gfx950) Hough-transform track finder.
+ *
+ * The paper's method (Section 3, "Hough Transform Algorithm") has two steps:
+ * every hit adds votes to the cells of a discretised (curvature, azimuth)
+ * parameter space that are consistent with it, and cells with many votes are
+ * then found as local maxima of that space.  This library computes:
+ *
+ *   hough_vote       step 1: per event, a uint16 layer-bitmask accumulator
+ *                    A[d0][q/pT][phi0] (a cell holds the OR of 1 << layer of
+ *                    every hit voting into it; its vote count is the popcount)
+ *   hough_peaks      step 2: cells with popcount >= threshold that are >= all
+ *                    neighbours in their 3x3 (q/pT, phi0) window, 3x3x3 with
+ *                    a d0 axis; phi0 wraps, q/pT and d0 do not
+ *   hough_rz_refine  the confirmation step the paper leaves to "more
+ *                    expensive computations" (end of the first paragraph of
+ *                    Section 3): per candidate cell, its member hits vote in
+ *                    a (cot theta, z0) grid and the argmax is reported
+ *
+ * Geometry.  Curvature rho = 0.299792458e-3 * b_tesla * q/pT [1/mm]; B along
+ * +z; positive q/pT bends clockwise.  A track with perigee (d0, phi0) crosses
+ * radius r at phi = phi0 + asin((d0 - rho (r^2 + d0^2)/2) / (r (1 - rho d0))).
+ * Angles are uint32 turn fractions (2^32 == one full turn); phi0 bin p covers
+ * [p, p+1) * 2^32 / n_phi.  The library tabulates, once per context in FP64
+ * on the host, O[l][d][k] = llround(asin(arg) / 2pi * 2^32) for the bin-centre
+ * track of row (d, k) at layer radius l, so a vote is one subtract and one
+ * shift: p = (phi - O[l][d][k]) >> (32 - log2 n_phi).  Rows whose layer is
+ * unreachable (1 - rho d0 <= 0 or |arg| > 1) receive no vote.  The rz stage
+ * uses Z[k][l][j] = llround(cot_j * s_l(k) * 1000) um with s = (2/rho)
+ * asin(rho r / 2) the transverse arc length (s = r when rho == 0), then
+ * z0 = z - Z and z0 bin b = floor((z0 - z0_lo) * n_z0 / (z0_hi - z0_lo)).
+ * Bin centres: kappa_k = qpt_lo + (k + 0.5) (qpt_hi - qpt_lo) / n_qpt, and
+ * likewise for d0 (d0 = 0 exactly when n_d0 == 1) and cot.
+ *
+ * Conventions for every call below:
+ *   - Pointers named "device" are HIP device pointers; everything else is host.
+ *   - Stream arguments are hipStream_t values passed as void* (NULL = the
+ *     null stream).  Calls enqueue work on that stream and return without
+ *     waiting for it; argument checks happen synchronously, before anything
+ *     is enqueued.  The hot calls allocate nothing and never synchronise the
+ *     host, so they may be captured into a HIP graph.
+ *   - The caller owns every hit, accumulator and output buffer.  The context
+ *     owns its tables and scratch, sized at hough_create from hough_limits;
+ *     calls that share a context must not overlap in time (one stream per
+ *     context, or external ordering).
+ *   - Return value: HOUGH_OK (0) or a negative hough_status; on
+ *     HOUGH_EDEVICE the HIP error text is kept for hough_last_error().
+ */
+#ifndef HOUGH_H
+#define HOUGH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HOUGH_OK = 0,
+    HOUGH_EINVAL = -1,      /* invalid spec, limits or argument */
+    HOUGH_ENOMEM = -2,      /* device or host allocation failed at create */
+    HOUGH_EDEVICE = -3,     /* a HIP runtime call failed */
+    HOUGH_ECAPACITY = -4,   /* reserved: capacity overflow is reported through offsets */
+    HOUGH_ELIMIT = -5       /* call exceeds the limits given at hough_create */
+} hough_status;
+
+typedef struct hough_ctx hough_ctx;
+typedef struct hough_graph hough_graph;
+
+/* Parameter-space grid.  Accumulator rows are (d, k) pairs, d-major; a row
+ * holds n_phi cells.  Cell index = (d * n_qpt + k) * n_phi + p. */
+typedef struct {
+    uint32_t n_layers;              /* 1..16; bit l of a mask = layer l */
+    double   layer_r_mm[16];        /* strictly ascending, > 0 */
+    double   b_tesla;
+    uint32_t n_qpt;                 /* >= 1 */
+    double   qpt_lo, qpt_hi;        /* q/pT range, 1/GeV */
+    uint32_t n_phi;                 /* power of two, 2..65536 */
+    uint32_t n_d0;                  /* >= 1; 1 means prompt (d0 = 0) */
+    double   d0_lo_mm, d0_hi_mm;
+    uint32_t threshold;             /* peak needs popcount >= threshold */
+    uint32_t n_z0;                  /* 0 disables the rz stage; else 1..65535 */
+    int32_t  z0_lo_um, z0_hi_um;    /* z0_hi > z0_lo */
+    uint32_t n_cot;                 /* 1..65535 when n_z0 > 0 */
+    double   cot_lo, cot_hi;
+    uint32_t rz_max_candidates;     /* 0: every peak; else the first this many
+                                       peaks by (popcount desc, cell asc) */
+} hough_grid_spec;
+
+/* Upper bounds of any single call, fixing the context's scratch. */
+typedef struct {
+    uint32_t max_events;            /* events per call, >= 1 */
+    uint64_t max_hits;              /* hits per call (all events), < 2^32 */
+    uint64_t max_peaks;             /* reserved (peak buffers are the caller's); may be 0 */
+} hough_limits;
+
+/* Hits of n_events events, concatenated (structure of arrays). */
+typedef struct {
+    const uint8_t  *layer;          /* device [n_hits]; values >= n_layers are ignored */
+    const uint32_t *phi;            /* device [n_hits]; uint32 turn fraction */
+    const int32_t  *z_um;           /* device [n_hits]; z in micrometres (rz only, else may be NULL) */
+    const uint64_t *event_offsets;  /* device [n_events + 1]; event e = [off[e], off[e+1]);
+                                       out-of-range offsets are clamped to [0, n_hits] */
+    uint32_t n_events;              /* host copy */
+    uint64_t n_hits;                /* host copy */
+} hough_hits;
+
+/* One local maximum. */
+typedef struct {
+    uint32_t cell;                  /* index within its event's accumulator */
+    uint16_t mask;                  /* the cell's layer mask */
+    uint16_t popcount;              /* number of layers in the mask */
+} hough_peak;
+
+/* One rz refinement result. */
+typedef struct {
+    uint32_t peak;                  /* index of the candidate in its event's peak list */
+    uint16_t cot_bin, z0_bin;       /* argmax; ties -> smallest cot bin, then z0 bin */
+    uint32_t count;                 /* member votes in that (cot, z0) bin */
+    uint32_t n_members;             /* hits that voted into the candidate's cell */
+} hough_rz;
+
+/* Autotuning knobs of the kernels (all 0 = library default). */
+typedef struct {
+    uint32_t vote_rows;             /* accumulator rows per LDS tile */
+    uint32_t vote_threads;          /* threads per vote workgroup (multiple of 64, <= 1024) */
+    uint32_t vote_wgs_per_cu;       /* persistent vote grid: workgroups per compute unit */
+    uint32_t peak_rows;             /* accumulator rows per peak-finding tile */
+    uint32_t rz_waves_per_cu;       /* persistent rz grid: waves per compute unit */
+    uint32_t vote_algo;             /* 0 = default, 1 = LDS atomic scatter, 2 = global atomics */
+    uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
+} hough_tuning;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Validates the spec (rules in the field comments; the rz stage needs
+ * n_d0 == 1), builds the FP64 tables on the host, allocates tables and
+ * scratch on `device` and uploads the tables (a blocking host-to-device
+ * copy, done once).  *out receives the context; nothing is allocated on
+ * failure.  Returns HOUGH_EINVAL, HOUGH_ENOMEM or HOUGH_EDEVICE on error. */
+int hough_create(const hough_grid_spec *spec, const hough_limits *limits,
+                 int device, hough_ctx **out);
+
+/* Frees the context's device memory.  NULL is accepted.  Work still
+ * enqueued with this context must have completed. */
+void hough_destroy(hough_ctx *ctx);
+
+/* ---- hot path ---------------------------------------------------------- */
+
+/* Step 1, voting (Section 3: increment the voxels each hit maps to; the
+ * Discussion's A[B[i]] += 1 in its layer-mask form).  For every event e,
+ * every hit h of e with layer l < n_layers and every reachable row (d, k):
+ *     acc[e][d][k][(phi_h - O[l][d][k]) >> (32 - log2 n_phi)] |= 1 << l.
+ * acc: device, n_events * n_d0 * n_qpt * n_phi uint16, fully overwritten
+ * (no need to clear it).  Requires n_events <= max_events and
+ * n_hits <= max_hits (HOUGH_ELIMIT).  hits->z_um is not read. */
+int hough_vote(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, void *stream);
+
+/* Step 2, local maxima (Section 3: finding cells with many votes amounts to
+ * looking for local maxima).  A cell c of event e is a peak iff
+ * popcount(acc[c]) >= threshold and popcount(acc[c]) >= popcount of each
+ * neighbour (3x3 in (q/pT, phi0), 3x3x3 when n_d0 > 1; phi0 periodic,
+ * missing q/pT or d0 neighbours ignored).  Peaks of event 0, then event 1,
+ * ..., each in ascending cell order, are written to `peaks` (device,
+ * `capacity` records); event e's peaks are [off[e], off[e+1]) with
+ * off = event_peak_offsets (device, n_events + 1 uint64, written by the
+ * call).  When the total exceeds capacity, records past capacity are dropped
+ * and the offsets still hold the true counts: compare off[n_events] with
+ * capacity after the stream completes. */
+int hough_peaks(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events,
+                hough_peak *peaks, uint64_t capacity, uint64_t *event_peak_offsets,
+                void *stream);
+
+/* Confirmation: rz refinement of the candidates of each event (needs
+ * n_z0 > 0).  Candidates of event e are its peaks in list order, or, when
+ * rz_max_candidates = M > 0, the first M of them ordered by (popcount
+ * descending, cell ascending).  For a candidate with cell (k, p), members
+ * are the hits of e that voted into that exact cell; every member votes once
+ * per cot bin j at b = floor((z - Z[k][l][j] - z0_lo) * n_z0 / (z0_hi -
+ * z0_lo)) when 0 <= b < n_z0.  The record holds the (j, b) of the largest
+ * count (ties -> smallest j, then smallest b; all-zero -> (0, 0), count 0).
+ * Records of event e are [roff[e], roff[e+1]) of `out` (device, `capacity`
+ * records) in candidate order, roff = event_rz_offsets (device, n_events + 1
+ * uint64, written by the call); overflow is handled as in hough_peaks.
+ * `hits` must be the hits the peaks were found from, with z_um set;
+ * peaks (device, peak_capacity records) and event_peak_offsets (device) are
+ * hough_peaks' outputs; peaks it dropped for lack of capacity are not seen.
+ * When rz_max_candidates > 0 the context holds max_events *
+ * rz_max_candidates candidate indices of scratch. */
+int hough_rz_refine(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks,
+                    uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
+                    uint64_t capacity, uint64_t *event_rz_offsets, void *stream);
+
+/* ---- HIP graph of the whole path (batched mode) ------------------------ */
+
+/* Captures vote -> peaks [-> rz when rz_out != NULL] for these exact buffers
+ * into a HIP graph, so that one hough_graph_launch replays the whole batch
+ * with one host call.  The buffers must stay valid while the graph lives;
+ * their contents may change between launches, their sizes may not.  The
+ * capture uses `stream` and leaves it idle. */
+int hough_graph_capture(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc,
+                        hough_peak *peaks, uint64_t peak_capacity, uint64_t *event_peak_offsets,
+                        hough_rz *rz_out, uint64_t rz_capacity, uint64_t *event_rz_offsets,
+                        void *stream, hough_graph **out);
+int hough_graph_launch(hough_graph *graph, void *stream);
+void hough_graph_destroy(hough_graph *graph);
+
+/* ---- helpers (not on the hot path) ------------------------------------ */
+
+/* HOUGH_OK if the spec is valid, else HOUGH_EINVAL.  Host only. */
+int hough_check_spec(const hough_grid_spec *spec);
+
+/* The library's own host tables, for inspection: O and V as [l][d][k]
+ * (n_layers * n_d0 * n_qpt entries each, V = 1 if reachable), Z as [k][l][j]
+ * (n_qpt * n_layers * n_cot entries; may be NULL when n_z0 == 0).  Host
+ * only, needs no device.  Buffer sizes are checked against nOV and nZ. */
+int hough_build_tables(const hough_grid_spec *spec, uint32_t *O, uint8_t *V, size_t nOV,
+                       int32_t *Z, size_t nZ);
+
+/* Kernel tuning.  Values outside the supported set give HOUGH_EINVAL and
+ * leave the previous tuning in place. */
+int hough_set_tuning(hough_ctx *ctx, const hough_tuning *tuning);
+int hough_get_tuning(const hough_ctx *ctx, hough_tuning *tuning);
+
+/* Per-kernel timing: when enabled, every kernel launch is bracketed by HIP
+ * events on its stream.  hough_kernel_times() synchronises those events and
+ * fills up to `n` entries (name, launches, total milliseconds), returning
+ * the number of distinct kernels; hough_kernel_times_reset() clears them. */
+int hough_set_profiling(hough_ctx *ctx, int enable);
+int hough_kernel_times(hough_ctx *ctx, const char **names, uint64_t *launches,
+                       double *total_ms, int n);
+void hough_kernel_times_reset(hough_ctx *ctx);
+
+const char *hough_strerror(int status);
+const char *hough_last_error(const hough_ctx *ctx);
+/* Number of compute units of the context's device. */
+int hough_device_cus(const hough_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOUGH_H */

@@ -1,0 +1,406 @@
+// C ABI of the track finder: context lifetime, argument checks, the hot-path
+// entry points, HIP-graph capture of the whole path and per-kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "hough_internal.h"
+
+using namespace hough;
+
+namespace {
+
+constexpr uint32_t kMaxRzWavesPerCu = 16;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int device_error(hough_ctx *c, hipError_t e, const char *where)
+{
+    if (c) {
+        c->last_error = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return HOUGH_EDEVICE;
+}
+
+template <typename T>
+bool dev_alloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) return true;
+    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)) == hipSuccess;
+}
+
+void free_all(hough_ctx *c)
+{
+    void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
+                    c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
+                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &t : c->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+}
+
+bool hits_ok(const hough_ctx *c, const hough_hits *h, bool need_z)
+{
+    if (!h) return false;
+    if (h->n_events == 0) return true;
+    if (!h->event_offsets) return false;
+    if (h->n_hits && (!h->layer || !h->phi)) return false;
+    if (need_z && h->n_hits && !h->z_um) return false;
+    (void)c;
+    return true;
+}
+
+bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
+{
+    if (t.vote_rows) {
+        if (t.vote_rows > 64 || (t.vote_rows & (t.vote_rows - 1))) return false;
+        if (size_t(t.vote_rows) * c->spec.n_phi * 4 > c->max_lds) return false;
+    }
+    if (t.vote_threads && (t.vote_threads % 64 || t.vote_threads > 1024)) return false;
+    if (t.vote_wgs_per_cu > 32) return false;
+    if (t.peak_rows > 4096) return false;
+    if (t.rz_waves_per_cu > kMaxRzWavesPerCu) return false;
+    if (t.vote_algo > 2) return false;
+    if (t.rz_slow_path > 1) return false;
+    return true;
+}
+
+}  // namespace
+
+namespace hough {
+
+void prof_begin(hough_ctx *c, const char *name, hipStream_t s, KernelTimer *t)
+{
+    t->name = nullptr;
+    if (!c->prof || c->capturing) return;
+    for (int i = 0; i < 2; ++i) {
+        hipEvent_t ev;
+        if (c->event_pool.empty()) {
+            if (hipEventCreate(&ev) != hipSuccess) return;
+        } else {
+            ev = c->event_pool.back();
+            c->event_pool.pop_back();
+        }
+        (i ? t->stop : t->start) = ev;
+    }
+    t->name = name;
+    (void)hipEventRecord(t->start, s);
+}
+
+void prof_end(hough_ctx *c, hipStream_t s, KernelTimer *t)
+{
+    if (!t->name) return;
+    (void)hipEventRecord(t->stop, s);
+    c->pending.push_back(*t);
+}
+
+}  // namespace hough
+
+extern "C" {
+
+const char *hough_strerror(int status)
+{
+    switch (status) {
+    case HOUGH_OK: return "ok";
+    case HOUGH_EINVAL: return "invalid argument";
+    case HOUGH_ENOMEM: return "out of memory";
+    case HOUGH_EDEVICE: return "HIP runtime error";
+    case HOUGH_ECAPACITY: return "capacity exceeded";
+    case HOUGH_ELIMIT: return "call exceeds context limits";
+    default: return "unknown status";
+    }
+}
+
+const char *hough_last_error(const hough_ctx *ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "";
+}
+
+int hough_check_spec(const hough_grid_spec *spec)
+{
+    return spec && spec_valid(*spec) ? HOUGH_OK : HOUGH_EINVAL;
+}
+
+int hough_build_tables(const hough_grid_spec *spec, uint32_t *O, uint8_t *V, size_t nOV,
+                       int32_t *Z, size_t nZ)
+{
+    if (!spec || !spec_valid(*spec) || !O || !V) return HOUGH_EINVAL;
+    const size_t need = size_t(spec->n_layers) * spec->n_d0 * spec->n_qpt;
+    if (nOV < need) return HOUGH_EINVAL;
+    build_offsets(*spec, O, V);
+    if (Z) {
+        const size_t needz = size_t(spec->n_qpt) * spec->n_layers * spec->n_cot;
+        if (!spec->n_z0 || nZ < needz) return HOUGH_EINVAL;
+        build_zshift(*spec, Z);
+    }
+    return HOUGH_OK;
+}
+
+int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int device, hough_ctx **out)
+{
+    if (!out) return HOUGH_EINVAL;
+    *out = nullptr;
+    if (!spec || !limits || !spec_valid(*spec)) return HOUGH_EINVAL;
+    if (limits->max_events < 1 || limits->max_hits >= (uint64_t(1) << 32)) return HOUGH_EINVAL;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return HOUGH_EINVAL;
+    DeviceGuard guard(device);
+
+    hough_ctx *c = new (std::nothrow) hough_ctx;
+    if (!c) return HOUGH_ENOMEM;
+    c->spec = *spec;
+    c->lim = *limits;
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->n_cu = cus;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = std::min<size_t>(size_t(lds) - 512, 65536);   // headroom for static LDS
+    while ((1u << c->log2_phi) < spec->n_phi) ++c->log2_phi;
+    c->shift = 32 - c->log2_phi;
+    c->rows = spec->n_d0 * spec->n_qpt;
+    c->cells = uint64_t(c->rows) * spec->n_phi;
+    const bool rz = spec->n_z0 > 0;
+    c->bucket_bits = rz ? std::min(c->log2_phi + 2, kMaxBucketBits) : 0;
+
+    // host tables
+    const size_t nOV = size_t(spec->n_layers) * c->rows;
+    std::vector<uint32_t> O(nOV);
+    std::vector<uint8_t> V(nOV);
+    build_offsets(*spec, O.data(), V.data());
+    c->all_valid = std::all_of(V.begin(), V.end(), [](uint8_t v) { return v != 0; });
+    std::vector<int32_t> Z;
+    if (rz) {
+        Z.resize(size_t(spec->n_qpt) * spec->n_layers * spec->n_cot);
+        build_zshift(*spec, Z.data());
+    }
+
+    const uint64_t H = limits->max_hits ? limits->max_hits : 1;
+    const uint32_t E = limits->max_events;
+    const uint32_t L = spec->n_layers;
+    c->n_peak_tiles = std::max<uint64_t>(uint64_t(E) * c->rows, E);
+    const size_t nb = rz ? (size_t(1) << c->bucket_bits) + 1 : 0;
+    const size_t ncand = rz ? size_t(E) * spec->rz_max_candidates : 0;
+    const size_t rzh = rz ? size_t(c->n_cu) * kMaxRzWavesPerCu * spec->n_z0 : 0;
+    bool ok = dev_alloc(&c->d_O, nOV) && dev_alloc(&c->d_V, nOV) && dev_alloc(&c->d_Z, Z.size()) &&
+              dev_alloc(&c->d_phi_a, H) && dev_alloc(&c->d_z_a, rz ? H : 0) &&
+              dev_alloc(&c->d_phi_b, rz ? H : 0) && dev_alloc(&c->d_z_b, rz ? H : 0) &&
+              dev_alloc(&c->d_layer_off, size_t(E) * (L + 1)) &&
+              dev_alloc(&c->d_bucket_off, size_t(E) * L * nb) && dev_alloc(&c->d_order, E) &&
+              dev_alloc(&c->d_counters, 64) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&
+              dev_alloc(&c->d_tile_off, c->n_peak_tiles + 1) && dev_alloc(&c->d_cand, ncand) &&
+              dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh);
+    if (!ok) {
+        free_all(c);
+        delete c;
+        return HOUGH_ENOMEM;
+    }
+    hipError_t err = hipMemcpy(c->d_O, O.data(), nOV * 4, hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = hipMemcpy(c->d_V, V.data(), nOV, hipMemcpyHostToDevice);
+    if (err == hipSuccess && rz) err = hipMemcpy(c->d_Z, Z.data(), Z.size() * 4, hipMemcpyHostToDevice);
+    if (err == hipSuccess && rzh) err = hipMemset(c->d_rz_hist, 0, rzh * 4);
+    if (err == hipSuccess) err = hipMemset(c->d_counters, 0, 64 * 4);
+    if (err == hipSuccess) err = hipDeviceSynchronize();
+    if (err != hipSuccess) {
+        free_all(c);
+        delete c;
+        return HOUGH_EDEVICE;
+    }
+    *out = c;
+    return HOUGH_OK;
+}
+
+void hough_destroy(hough_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceGuard guard(ctx->device);
+    free_all(ctx);
+    delete ctx;
+}
+
+int hough_vote(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, void *stream)
+{
+    if (!ctx || !hits_ok(ctx, hits, false) || (hits->n_events && !acc)) return HOUGH_EINVAL;
+    if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_vote(ctx, hits, acc, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_vote");
+}
+
+int hough_peaks(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
+                uint64_t capacity, uint64_t *event_peak_offsets, void *stream)
+{
+    if (!ctx || !event_peak_offsets || (n_events && !acc) || (capacity && !peaks)) return HOUGH_EINVAL;
+    if (n_events > ctx->lim.max_events) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_peaks(ctx, acc, n_events, peaks, capacity, event_peak_offsets,
+                                      static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peaks");
+}
+
+int hough_rz_refine(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks,
+                    uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
+                    uint64_t capacity, uint64_t *event_rz_offsets, void *stream)
+{
+    if (!ctx || !ctx->spec.n_z0 || !hits_ok(ctx, hits, true) || !event_peak_offsets ||
+        !event_rz_offsets || (peak_capacity && !peaks) || (capacity && !out))
+        return HOUGH_EINVAL;
+    if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_rz(ctx, hits, peaks, peak_capacity, event_peak_offsets, out, capacity,
+                                   event_rz_offsets, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_rz_refine");
+}
+
+struct hough_graph {
+    hough_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int hough_graph_capture(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, hough_peak *peaks,
+                        uint64_t peak_capacity, uint64_t *event_peak_offsets, hough_rz *rz_out,
+                        uint64_t rz_capacity, uint64_t *event_rz_offsets, void *stream,
+                        hough_graph **out)
+{
+    if (!out) return HOUGH_EINVAL;
+    *out = nullptr;
+    const bool with_rz = rz_out != nullptr || event_rz_offsets != nullptr;
+    if (!ctx || !stream || !hits_ok(ctx, hits, with_rz) || !acc || !event_peak_offsets ||
+        (peak_capacity && !peaks) || (with_rz && (!ctx->spec.n_z0 || !event_rz_offsets)))
+        return HOUGH_EINVAL;
+    if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hough_graph *g = new (std::nothrow) hough_graph;
+    if (!g) return HOUGH_ENOMEM;
+    g->ctx = ctx;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        return device_error(ctx, e, "hipStreamBeginCapture");
+    }
+    ctx->capturing = true;
+    hipError_t le = launch_vote(ctx, hits, acc, s);
+    if (le == hipSuccess) le = launch_peaks(ctx, acc, hits->n_events, peaks, peak_capacity, event_peak_offsets, s);
+    if (le == hipSuccess && with_rz)
+        le = launch_rz(ctx, hits, peaks, peak_capacity, event_peak_offsets, rz_out, rz_capacity,
+                       event_rz_offsets, s);
+    ctx->capturing = false;
+    e = hipStreamEndCapture(s, &g->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return device_error(ctx, le != hipSuccess ? le : e, "graph capture");
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g->graph);
+        delete g;
+        return device_error(ctx, e, "hipGraphInstantiate");
+    }
+    *out = g;
+    return HOUGH_OK;
+}
+
+int hough_graph_launch(hough_graph *graph, void *stream)
+{
+    if (!graph || !graph->exec) return HOUGH_EINVAL;
+    DeviceGuard guard(graph->ctx->device);
+    const hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(graph->ctx, e, "hipGraphLaunch");
+}
+
+void hough_graph_destroy(hough_graph *graph)
+{
+    if (!graph) return;
+    DeviceGuard guard(graph->ctx->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
+int hough_set_tuning(hough_ctx *ctx, const hough_tuning *tuning)
+{
+    if (!ctx || !tuning || !tuning_ok(ctx, *tuning)) return HOUGH_EINVAL;
+    ctx->tun = *tuning;
+    return HOUGH_OK;
+}
+
+int hough_get_tuning(const hough_ctx *ctx, hough_tuning *tuning)
+{
+    if (!ctx || !tuning) return HOUGH_EINVAL;
+    *tuning = ctx->tun;
+    return HOUGH_OK;
+}
+
+int hough_set_profiling(hough_ctx *ctx, int enable)
+{
+    if (!ctx) return HOUGH_EINVAL;
+    ctx->prof = enable != 0;
+    return HOUGH_OK;
+}
+
+int hough_kernel_times(hough_ctx *ctx, const char **names, uint64_t *launches, double *total_ms, int n)
+{
+    if (!ctx) return HOUGH_EINVAL;
+    DeviceGuard guard(ctx->device);
+    for (auto &t : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            auto it = std::find_if(ctx->stats.begin(), ctx->stats.end(),
+                                   [&](const KernelStat &s) { return s.name == t.name; });
+            if (it == ctx->stats.end()) {
+                ctx->stats.push_back(KernelStat{t.name, 0, 0.0});
+                it = ctx->stats.end() - 1;
+            }
+            it->launches += 1;
+            it->total_ms += ms;
+        }
+        ctx->event_pool.push_back(t.start);
+        ctx->event_pool.push_back(t.stop);
+    }
+    ctx->pending.clear();
+    const int m = int(ctx->stats.size());
+    for (int i = 0; i < m && i < n; ++i) {
+        if (names) names[i] = ctx->stats[i].name.c_str();
+        if (launches) launches[i] = ctx->stats[i].launches;
+        if (total_ms) total_ms[i] = ctx->stats[i].total_ms;
+    }
+    return m;
+}
+
+void hough_kernel_times_reset(hough_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hough_kernel_times(ctx, nullptr, nullptr, nullptr, 0);
+    ctx->stats.clear();
+}
+
+int hough_device_cus(const hough_ctx *ctx)
+{
+    return ctx ? ctx->n_cu : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// Exact unsigned 32-bit division by a run-time invariant divisor through a
+// multiply-high, after T. Granlund and P. L. Montgomery, "Division by
+// Invariant Integers using Multiplication" (PLDI 1994), figure 4.1:
+// with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+//   t = mulhi(m, n);  q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0)
+// equals floor(n / d) for every 32-bit n and every d >= 1.
+#pragma once
+
+#include <cstdint>
+
+#ifndef HOUGH_HD
+#if defined(__HIPCC__)
+#define HOUGH_HD __host__ __device__
+#else
+#define HOUGH_HD
+#endif
+#endif
+
+namespace hough {
+
+struct FastDiv32 {
+    uint32_t m = 1;
+    uint32_t sh1 = 0;
+    uint32_t sh2 = 0;
+};
+
+inline FastDiv32 make_fastdiv32(uint32_t d)
+{
+    FastDiv32 f;
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;
+    f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    f.sh1 = l < 1 ? l : 1;
+    f.sh2 = l > 0 ? l - 1 : 0;
+    return f;
+}
+
+HOUGH_HD inline uint32_t fastdiv32(uint32_t n, const FastDiv32 &f)
+{
+    const uint32_t t = uint32_t((uint64_t(f.m) * n) >> 32);
+    return (t + ((n - t) >> f.sh1)) >> f.sh2;
+}
+
+}  // namespace hough

@@ -1,0 +1,115 @@
+// Internal declarations of the MI355X Hough-transform library: the context,
+// host tables and the launchers of every kernel.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hough.h"
+#include "tables.h"
+
+// A kernel's dynamically sized LDS array (its byte size is given at launch).
+#ifndef HOUGH_DYNAMIC_LDS
+#define HOUGH_DYNAMIC_LDS(type, name) extern __shared__ type name[]
+#endif
+
+namespace hough {
+
+// Coarse azimuth buckets used to find the member hits of an rz candidate:
+// log2(n_phi) + 2 bits, at most 12 (4096 buckets per layer).
+constexpr uint32_t kMaxBucketBits = 12;
+
+struct KernelTimer {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+struct KernelStat {
+    std::string name;
+    uint64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+}  // namespace hough
+
+struct hough_ctx {
+    hough_grid_spec spec{};
+    hough_limits lim{};
+    hough_tuning tun{};
+    int device = 0;
+    int n_cu = 256;
+    size_t max_lds = 65536;
+
+    uint32_t log2_phi = 0;
+    uint32_t shift = 0;          // 32 - log2_phi
+    uint32_t rows = 0;           // n_d0 * n_qpt
+    uint64_t cells = 0;          // rows * n_phi
+    uint32_t bucket_bits = 0;    // rz member search buckets (0 when no rz)
+
+    // tables (device)
+    uint32_t *d_O = nullptr;     // [L][rows]
+    uint8_t *d_V = nullptr;      // [L][rows]
+    int32_t *d_Z = nullptr;      // [n_qpt][L][n_cot]
+    bool all_valid = true;       // every (layer, row) reachable
+
+    // scratch (device)
+    uint32_t *d_phi_a = nullptr;     // [max_hits] hits grouped by layer
+    int32_t *d_z_a = nullptr;        // [max_hits]
+    uint32_t *d_phi_b = nullptr;     // [max_hits] grouped by (layer, bucket) for rz
+    int32_t *d_z_b = nullptr;        // [max_hits]
+    uint32_t *d_layer_off = nullptr; // [max_events][L + 1] relative to the event start
+    uint32_t *d_bucket_off = nullptr;// [max_events][L][NB + 1]
+    uint32_t *d_order = nullptr;     // [max_events] events, longest first
+    uint32_t *d_counters = nullptr;  // [64] work-queue counters
+    uint32_t *d_tile_counts = nullptr; // [max peak tiles]
+    uint64_t *d_tile_off = nullptr;    // [max peak tiles + 1]
+    uint32_t *d_cand = nullptr;        // [max_events * rz_max_candidates]
+    uint32_t *d_cand_counts = nullptr; // [max_events]
+    uint32_t *d_rz_hist = nullptr;     // [rz blocks][n_z0] zeroed uint32 (rz slow path)
+    uint64_t n_peak_tiles = 0;
+
+    // profiling
+    bool prof = false;
+    bool capturing = false;
+    std::vector<hough::KernelTimer> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<hough::KernelStat> stats;
+
+    std::string last_error;
+};
+
+namespace hough {
+
+// Launch bracket for per-kernel timing (no-op unless profiling is enabled).
+void prof_begin(hough_ctx *c, const char *name, hipStream_t s, KernelTimer *t);
+void prof_end(hough_ctx *c, hipStream_t s, KernelTimer *t);
+
+// ---- launchers (each returns the HIP status of its launch) --------------
+hipError_t launch_fill_u32(hough_ctx *c, uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_bucket_layers(hough_ctx *c, const hough_hits *h, bool with_z, hipStream_t s);
+hipError_t launch_bucket_phi(hough_ctx *c, const hough_hits *h, hipStream_t s);
+hipError_t launch_event_order(hough_ctx *c, const hough_hits *h, hipStream_t s);
+hipError_t launch_vote(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
+hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
+                        uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s);
+hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
+                     uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
+                     uint64_t capacity, uint64_t *event_rz_offsets, hipStream_t s);
+uint32_t vote_rows(const hough_ctx *c);
+uint32_t rz_blocks(const hough_ctx *c);
+uint64_t max_peak_tiles(const hough_ctx *c);
+
+// Exclusive prefix of n uint32 counts into n + 1 uint64 offsets (one workgroup).
+hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
+                              uint64_t stride_out, uint64_t *out_strided, hipStream_t s);
+
+inline uint32_t peak_rows(const hough_ctx *c)
+{
+    return c->tun.peak_rows ? c->tun.peak_rows : 16u;
+}
+
+}  // namespace hough
