@@ -1,0 +1,255 @@
+"""Benchmark of the Hough-transform track finder on one MI355X.
+
+Prints one JSON line.  The headline step is one pass of the whole hot path
+(layer bucketing, vote, peak finding, rz refinement) over the 1000-track
+event with 10,000 noise hits on a 1024 x 1024 (q/pT, phi0) grid plus the
+256 x 256 (cot theta, z0) refinement, with its hits already resident in HBM.
+`value` is Hough votes per second: rphi votes (hits x q/pT rows) per step
+over the measured step time.  Per-kernel durations come from HIP events
+recorded on the kernels' own stream inside the timed region.
+
+Also reported, in the same line:
+  batched  -- 4096 events (lognormal sizes) as one captured HIP graph vs a
+              loop of per-event launches on the same GPU, with the vote
+              kernel's HBM roofline;
+  serving  -- the continuous-batching request loop (when --serving is on).
+  cpu_baseline -- the CPU oracle timed on this host on one full event.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Hough votes/s and events/s (1k-track event); batched vs plain; serving p99 latency"
+HBM_PEAK_GBS = 8000.0
+# int32 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# integer operations per rz (member, cot bin) vote: z - Z, - z0_lo, range
+# test, * n_z0, / span, histogram increment, running-maximum compare
+RZ_OPS_PER_VOTE = 7
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_avg_ms(times, name):
+    n, ms = times.get(name, (0, 0.0))
+    return ms / n if n else float("nan")
+
+
+def bench_single(H, torch, steps, warmup):
+    import synth
+    name = "c2_single_1ktrk_rz"
+    spec = synth.grid_spec(name)
+    ev = synth.gen_config(name)
+    ctx = H.HoughContext(spec, max_events=1, max_hits=ev.n_hits)
+    hits = H.DeviceHits.from_batch(ev)
+    acc = ctx.new_acc(1)
+    cap = ctx.cells
+    pk, poff = ctx.new_peaks(cap), ctx.new_offsets(1)
+    rz, roff = ctx.new_rz(cap), ctx.new_offsets(1)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.vote(hits, acc)
+        ctx.peaks(acc, 1, capacity=cap, peaks=pk, offsets=poff)
+        ctx.rz_refine(hits, pk, poff, peak_capacity=cap, capacity=cap, out=rz, offsets=roff)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.kernel_times_reset()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    times = ctx.kernel_times()
+    n_peaks = int(H.offsets_numpy(poff)[-1])
+    rzrec = H.rz_numpy(rz, roff)
+    members = int(rzrec["n_members"].astype(np.int64).sum())
+    rphi_votes = ev.n_hits * spec["n_qpt"] * spec["n_d0"]
+    rz_votes = members * spec["n_cot"]
+    ms = dt / steps * 1e3
+    stage = {k: round(v[1] / v[0], 5) for k, v in times.items() if v[0]}
+    dom = max(times, key=lambda k: times[k][1])
+    out = dict(ms_per_step=ms, rphi_votes=rphi_votes, rz_votes=rz_votes, n_peaks=n_peaks,
+               n_hits=ev.n_hits, stage_ms=stage, dominant=dom, stream=int(stream.cuda_stream))
+    # roofline of the dominant kernel
+    if dom == "rz_vote":
+        t = kernel_avg_ms(times, "rz_vote") * 1e-3
+        achieved = rz_votes * RZ_OPS_PER_VOTE / t / 1e12
+        out["roofline"] = dict(kernel="rz_vote", bound="alu", achieved=round(achieved, 4),
+                               peak=round(ALU_PEAK_TOPS, 2), unit="TOP/s",
+                               frac=round(achieved / ALU_PEAK_TOPS, 5), traffic=None,
+                               work_per_launch=f"{rz_votes} member x cot votes x {RZ_OPS_PER_VOTE} int ops")
+    else:
+        t = kernel_avg_ms(times, dom) * 1e-3
+        if dom == "vote_lds":
+            byts = 5 * ev.n_hits + 2 * ctx.cells
+        else:
+            byts = 2 * ctx.cells
+        gbs = byts / t / 1e9
+        out["roofline"] = dict(kernel=dom, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
+                               unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None)
+    out["rz_votes_per_s"] = rz_votes / (ms * 1e-3)
+    return out, (spec, ev)
+
+
+def bench_batched(H, torch, reps=5):
+    import synth
+    name = "c4_batch_4096"
+    spec = synth.grid_spec(name)
+    t0 = time.perf_counter()
+    batch = synth.gen_config(name)
+    log(f"c4: generated {batch.n_events} events, {batch.n_hits} hits in {time.perf_counter() - t0:.1f}s")
+    E = batch.n_events
+    ctx = H.HoughContext(spec, max_events=E, max_hits=batch.n_hits)
+    hits = H.DeviceHits.from_batch(batch)
+    acc = ctx.new_acc(E)
+    cap = E * ctx.cells
+    pk, poff = ctx.new_peaks(cap), ctx.new_offsets(E)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = ctx.graph_capture(hits, acc, pk, cap, poff, stream=stream)
+    g.launch(stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.launch(stream)
+    stream.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    total_peaks = int(H.offsets_numpy(poff)[-1])
+    # per-kernel times of the batched path (eager, same kernels, events on stream)
+    with torch.cuda.stream(stream):
+        ctx.kernel_times_reset()
+        ctx.set_profiling(True)
+        for _ in range(2):
+            ctx.vote(hits, acc, stream=stream)
+            ctx.peaks(acc, E, capacity=cap, peaks=pk, offsets=poff, stream=stream)
+        stream.synchronize()
+        ctx.set_profiling(False)
+        times = ctx.kernel_times()
+    t_vote = kernel_avg_ms(times, "vote_lds") * 1e-3
+    vote_bytes = 5 * batch.n_hits + 2 * E * ctx.cells
+    gbs = vote_bytes / t_vote / 1e9
+
+    # plain path: one event per launch, same kernels, same GPU
+    import ctypes as C
+    lib = ctx.lib
+    offs_dev = torch.zeros((E, 2), dtype=torch.int64, device="cuda")
+    sizes = np.diff(batch.offsets.astype(np.int64))
+    offs_dev[:, 1] = torch.from_numpy(sizes).cuda()
+    pctx = H.HoughContext(spec, max_events=1, max_hits=int(sizes.max()))
+    pacc = pctx.new_acc(1)
+    ppk, ppoff = pctx.new_peaks(pctx.cells), pctx.new_offsets(1)
+    structs = []
+    for e in range(E):
+        h = H.Hits()
+        a = int(batch.offsets[e])
+        h.layer = hits.layer.data_ptr() + a
+        h.phi = hits.phi.data_ptr() + 4 * a
+        h.z_um = None
+        h.event_offsets = offs_dev.data_ptr() + 16 * e
+        h.n_events = 1
+        h.n_hits = int(sizes[e])
+        structs.append(h)
+    sp = C.c_void_p(stream.cuda_stream)
+    acc_p, pk_p, poff_p = C.c_void_p(pacc.data_ptr()), C.c_void_p(ppk.data_ptr()), C.c_void_p(ppoff.data_ptr())
+
+    def plain():
+        for e in range(E):
+            lib.hough_vote(pctx._h, C.byref(structs[e]), acc_p, sp)
+            lib.hough_peaks(pctx._h, acc_p, 1, pk_p, pctx.cells, poff_p, sp)
+
+    plain()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    stream.synchronize()
+    t_plain = time.perf_counter() - t0
+    votes = batch.n_hits * spec["n_qpt"]
+    g.close()
+    return dict(
+        workload=name, n_events=E, n_hits=batch.n_hits, votes=votes, peaks=total_peaks,
+        graph_ms=round(t_graph * 1e3, 3), events_per_s=E / t_graph, votes_per_s=votes / t_graph,
+        plain_ms=round(t_plain * 1e3, 3), plain_events_per_s=E / t_plain,
+        speedup_vs_plain=round(t_plain / t_graph, 3),
+        stage_ms={k: round(v[1] / v[0], 4) for k, v in times.items() if v[0]},
+        roofline=dict(kernel="vote_lds", bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None,
+                      bytes_per_launch=vote_bytes))
+
+
+def cpu_baseline(spec, ev):
+    import oracle
+    tab = oracle.Tables(spec)
+    t0 = time.perf_counter()
+    A, pk, r = oracle.run_event(tab, ev.layer, ev.phi, ev.z)
+    dt = time.perf_counter() - t0
+    votes = ev.n_hits * spec["n_qpt"] * spec["n_d0"]
+    return dict(value=votes / dt, unit="votes/s", cores=1, kind="oracle", seconds=round(dt, 2),
+                sample=f"one full 1000-track event ({ev.n_hits} hits): vote, peaks and rz over all "
+                       f"{len(pk)} peaks, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serving", action="store_true", help="also run the serving sweep")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: events are independent, so more GPUs would "
+              "shard whole events with no exchange; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1310_7556_amd import hough as H
+    H.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    log("c2 single-event steps ...")
+    single, (spec, ev) = bench_single(H, torch, args.steps, args.warmup)
+    log(f"c2: {single['ms_per_step']:.3f} ms/step, dominant {single['dominant']}")
+    res = dict(
+        metric=METRIC, value=single["rphi_votes"] / (single["ms_per_step"] * 1e-3), unit="votes/s",
+        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(single["ms_per_step"], 4),
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="u32", data="synthetic",
+        config=dict(workload="c2_single_1ktrk_rz: 1000 prompt tracks + 10000 noise hits, 1024x1024 "
+                             "(q/pT, phi0) uint16 layer masks, threshold 8, rz 256x256",
+                    n_hits=single["n_hits"], grid=[1024, 1024], rz=[256, 256]),
+        events_per_s=1e3 / single["ms_per_step"],
+        rz_votes_per_s=single["rz_votes_per_s"],
+        peaks_per_event=single["n_peaks"],
+        stage_ms=single["stage_ms"],
+        roofline=single["roofline"],
+    )
+    if not args.no_batched:
+        log("c4 batched vs plain ...")
+        res["batched"] = bench_batched(H, torch)
+        log(f"c4: graph {res['batched']['graph_ms']} ms, plain {res['batched']['plain_ms']} ms")
+    if args.serving:
+        from paper_1310_7556_amd import serve
+        log("c5 serving sweep ...")
+        res["serving"] = serve.bench_serving(H, torch, log=log)
+    if not args.no_cpu:
+        log("cpu oracle baseline ...")
+        res["cpu_baseline"] = cpu_baseline(spec, ev)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
