@@ -130,6 +130,7 @@ typedef struct {
     uint32_t rz_waves_per_cu;       /* persistent rz grid: waves per compute unit */
     uint32_t vote_algo;             /* 0 = default, 1 = LDS atomic scatter, 2 = global atomics */
     uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
+    uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 8 or 16 */
 } hough_tuning;
 
 /* ---- context --------------------------------------------------------- */

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 
+#include "fastdiv.h"
 #include "hough_internal.h"
 
 using namespace hough;
@@ -46,7 +47,7 @@ bool dev_alloc(T **p, size_t count)
 
 void free_all(hough_ctx *c)
 {
-    void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
+    void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
                     c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist};
     for (void *p : ptrs)
@@ -81,6 +82,7 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.rz_waves_per_cu > kMaxRzWavesPerCu) return false;
     if (t.vote_algo > 2) return false;
     if (t.rz_slow_path > 1) return false;
+    if (t.rz_counter_bits != 0 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16) return false;
     return true;
 }
 
@@ -189,10 +191,26 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     std::vector<uint8_t> V(nOV);
     build_offsets(*spec, O.data(), V.data());
     c->all_valid = std::all_of(V.begin(), V.end(), [](uint8_t v) { return v != 0; });
-    std::vector<int32_t> Z;
+    std::vector<int32_t> Z, Zl;
     if (rz) {
         Z.resize(size_t(spec->n_qpt) * spec->n_layers * spec->n_cot);
         build_zshift(*spec, Z.data());
+        // fast rz path: with zl = Z + z0_lo in [-2^31, 2^31 - span], the
+        // uint32 difference u = z - zl is < span exactly when 0 <= z - zl <
+        // span for every int32 z; the bin is then one multiply-high
+        const int64_t span = int64_t(spec->z0_hi_um) - int64_t(spec->z0_lo_um);
+        const BinMagic bm = make_binmagic(uint64_t(span), spec->n_z0);
+        bool ok = bm.ok;
+        Zl.resize(Z.size());
+        for (size_t i = 0; ok && i < Z.size(); ++i) {
+            const int64_t zl = int64_t(Z[i]) + spec->z0_lo_um;
+            ok = zl >= INT32_MIN && zl <= int64_t(INT32_MAX) + 1 - span;
+            Zl[i] = int32_t(zl);
+        }
+        c->rz_fast = ok;
+        c->rz_magic_m = bm.m;
+        c->rz_magic_s = bm.s;
+        if (!ok) Zl.clear();
     }
 
     const uint64_t H = limits->max_hits ? limits->max_hits : 1;
@@ -203,6 +221,7 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     const size_t ncand = rz ? size_t(E) * spec->rz_max_candidates : 0;
     const size_t rzh = rz ? size_t(c->n_cu) * kMaxRzWavesPerCu * spec->n_z0 : 0;
     bool ok = dev_alloc(&c->d_O, nOV) && dev_alloc(&c->d_V, nOV) && dev_alloc(&c->d_Z, Z.size()) &&
+              dev_alloc(&c->d_Zl, Zl.size()) &&
               dev_alloc(&c->d_phi_a, H) && dev_alloc(&c->d_z_a, rz ? H : 0) &&
               dev_alloc(&c->d_phi_b, rz ? H : 0) && dev_alloc(&c->d_z_b, rz ? H : 0) &&
               dev_alloc(&c->d_layer_off, size_t(E) * (L + 1)) &&
@@ -218,6 +237,8 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     hipError_t err = hipMemcpy(c->d_O, O.data(), nOV * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(c->d_V, V.data(), nOV, hipMemcpyHostToDevice);
     if (err == hipSuccess && rz) err = hipMemcpy(c->d_Z, Z.data(), Z.size() * 4, hipMemcpyHostToDevice);
+    if (err == hipSuccess && !Zl.empty())
+        err = hipMemcpy(c->d_Zl, Zl.data(), Zl.size() * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess && rzh) err = hipMemset(c->d_rz_hist, 0, rzh * 4);
     if (err == hipSuccess) err = hipMemset(c->d_counters, 0, 64 * 4);
     if (err == hipSuccess) err = hipDeviceSynchronize();

@@ -41,4 +41,37 @@ HOUGH_HD inline uint32_t fastdiv32(uint32_t n, const FastDiv32 &f)
     return (t + ((n - t) >> f.sh1)) >> f.sh2;
 }
 
+// floor(u * nbins / span) for 0 <= u < span as one multiply-high and a
+// shift: b = (u * m) >> (32 + s) with m = ceil(nbins * 2^(32+s) / span) and
+// the smallest s >= 0 such that span^2 <= 2^(32+s).  Exact: u*m / 2^(32+s)
+// exceeds u*nbins/span by less than span / 2^(32+s) <= 1/span, while
+// u*nbins/span sits at least 1/span below the next integer (its fractional
+// part is r/span with r <= span - 1).  Usable when m < 2^32.
+struct BinMagic {
+    uint32_t m = 0;
+    uint32_t s = 0;
+    bool ok = false;
+};
+
+inline BinMagic make_binmagic(uint64_t span, uint32_t nbins)
+{
+    BinMagic b;
+    if (span == 0 || span >= (uint64_t(1) << 32) || nbins == 0) return b;
+    const unsigned __int128 sq = (unsigned __int128)span * span;
+    uint32_t s = 0;
+    while (((unsigned __int128)1 << (32 + s)) < sq) ++s;
+    const unsigned __int128 num = (unsigned __int128)nbins << (32 + s);
+    const unsigned __int128 m = (num + span - 1) / span;
+    if (m >= ((unsigned __int128)1 << 32)) return b;
+    b.m = uint32_t(m);
+    b.s = s;
+    b.ok = true;
+    return b;
+}
+
+HOUGH_HD inline uint32_t binmagic_apply(uint32_t u, uint32_t m, uint32_t s)
+{
+    return uint32_t(((uint64_t(u) * m) >> 32) >> s);
+}
+
 }  // namespace hough

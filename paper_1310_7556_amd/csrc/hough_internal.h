@@ -54,7 +54,12 @@ struct hough_ctx {
     uint32_t *d_O = nullptr;     // [L][rows]
     uint8_t *d_V = nullptr;      // [L][rows]
     int32_t *d_Z = nullptr;      // [n_qpt][L][n_cot]
+    int32_t *d_Zl = nullptr;     // [n_qpt][L][n_cot] = Z + z0_lo, when rz_fast
     bool all_valid = true;       // every (layer, row) reachable
+    // rz fast path: z - (Z + z0_lo) is exact in uint32 arithmetic and the z0
+    // bin is one multiply-high (see fastdiv.h BinMagic)
+    bool rz_fast = false;
+    uint32_t rz_magic_m = 0, rz_magic_s = 0;
 
     // scratch (device)
     uint32_t *d_phi_a = nullptr;     // [max_hits] hits grouped by layer

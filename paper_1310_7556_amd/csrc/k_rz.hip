@@ -10,12 +10,24 @@
 // and the record is the argmax over (j, b), ties to the smallest j then b.
 //
 // One 64-wide wavefront per candidate, persistent over a work counter.  A
-// lane owns cot bins j = lane, lane + 64, ... and a private uint16 z0
-// histogram column in LDS (hist[b * 64 + lane]): its running maximum is
-// exact because counts only grow, and the touched bins are cleared after
-// each cot bin.  A candidate with more than 65535 members (or a z0 grid too
-// large for LDS) takes a slower path through a uint32 histogram in global
-// scratch, one cot bin at a time.
+// lane owns cot bins j = lane, lane + 64, ... and a private column of z0
+// counters in LDS; its running maximum is exact because counts only grow.
+//
+// k_rz_vote_fast (used when the spec allows exact 32-bit arithmetic):
+//   1. lanes 0..L-1 each find their layer's window of azimuth buckets; a
+//      wave prefix over window lengths flattens all layers' scanned hits,
+//      and one ballot-compacted pass copies the members' z (grouped by layer)
+//      into LDS;
+//   2. per cot bin, per layer, per member: u = z - (Z + z0_lo) in uint32,
+//      in range iff u < span, bin by one multiply-high (BinMagic), and an
+//      LDS atomic add on a lane-private packed counter (8- or 16-bit) whose
+//      return value gives the running count without a read-modify-write
+//      chain;
+//   3. the counters are cleared wholesale with 16-byte stores.
+// A candidate with more members than the LDS list or the counter width
+// holds takes the slow path: a uint32 histogram in global scratch, one cot
+// bin at a time.  k_rz_vote is the general kernel (64-bit arithmetic) for
+// specs outside the fast path's range conditions.
 #include "fastdiv.h"
 #include "hough_internal.h"
 
@@ -30,6 +42,7 @@ struct RzParams {
     const uint32_t *O;            // [L][rows]
     const uint8_t *V;
     const int32_t *Z;             // [K][L][C]
+    const int32_t *Zl;            // [K][L][C] = Z + z0_lo (fast path)
     const uint2 *peaks;
     uint64_t peak_capacity;
     const uint64_t *poff;         // [E + 1]
@@ -45,7 +58,10 @@ struct RzParams {
     uint64_t span;                // z0_hi - z0_lo
     int use32;                    // span * n_z0 < 2^32: fast 32-bit division
     FastDiv32 fd;
-    int lds_ok;                   // the uint16 histogram fits in LDS
+    int lds_ok;                   // general kernel: the uint16 histogram fits in LDS
+    uint32_t bm, bs;              // fast path: bin = mulhi(u, bm) >> bs
+    uint32_t hw;                  // fast path: counter dwords per lane
+    uint32_t mcap;                // fast path: member list capacity
 };
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -93,6 +109,105 @@ __device__ __forceinline__ void for_members(const RzParams &P, uint64_t eb, cons
     }
 }
 
+// Slow path for one candidate: one cot bin at a time, lanes stride over the
+// members, counts in a zeroed uint32 histogram g[n_z0] in global scratch
+// (left zeroed on return).  Results are wave-uniform.
+__device__ void rz_slow(const RzParams &P, uint64_t eb, const uint32_t *bo, uint32_t k, uint32_t p,
+                        uint32_t mask, uint32_t *g, uint32_t lane, uint32_t &best_c, uint32_t &best_j,
+                        uint32_t &best_b)
+{
+    best_c = 0;
+    best_j = 0;
+    best_b = 0;
+    for (uint32_t j = 0; j < P.n_cot; ++j) {
+        for (int pass = 0; pass < 3; ++pass) {
+            uint32_t seen = 0, bc = 0, bb = 0;
+            for_members(P, eb, bo, k, p, mask, [&](uint32_t h, uint32_t l) {
+                if ((seen++ & 63u) != lane) return;
+                const int64_t zl = int64_t(P.Z[(size_t(k) * P.n_layers + l) * P.n_cot + j]) + P.z0_lo;
+                const int32_t b = z0_bin(P, P.z[eb + h], zl);
+                if (b < 0) return;
+                if (pass == 0) {
+                    atomicAdd(&g[b], 1u);
+                } else if (pass == 1) {
+                    const uint32_t cnt = __atomic_load_n(&g[b], __ATOMIC_RELAXED);
+                    if (cnt > bc || (cnt == bc && uint32_t(b) < bb)) { bc = cnt; bb = uint32_t(b); }
+                } else {
+                    g[b] = 0;
+                }
+            });
+            // every lane's updates of this pass are complete and visible
+            // before any lane starts the next pass
+            __threadfence();
+            __syncthreads();
+            if (pass == 1) {
+                // wave argmax of (count desc, bin asc) for this cot bin
+                uint64_t key = (uint64_t(bc) << 32) | (0xFFFFFFFFu - bb);
+                for (int off = 32; off > 0; off >>= 1) {
+                    const uint64_t o = __shfl_xor(key, off, 64);
+                    key = o > key ? o : key;
+                }
+                const uint32_t cc = uint32_t(key >> 32), b = 0xFFFFFFFFu - uint32_t(key);
+                if (cc > best_c) { best_c = cc; best_j = j; best_b = cc ? b : 0; }
+            }
+        }
+    }
+}
+
+// Wave argmax of (count desc, cot asc, z0 asc) over the lanes' bests, then
+// every lane stores the (uniform) record of candidate c.
+__device__ __forceinline__ void rz_finish(const RzParams &P, uint64_t c, uint32_t pk, uint32_t nm,
+                                          uint32_t best_c, uint32_t best_j, uint32_t best_b)
+{
+    uint64_t key = (uint64_t(best_c) << 32) | (uint64_t(0xFFFFu - (best_j & 0xFFFFu)) << 16) |
+                   (0xFFFFu - (best_b & 0xFFFFu));
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+    }
+    const uint32_t cnt = uint32_t(key >> 32);
+    const uint32_t jj = 0xFFFFu - uint32_t((key >> 16) & 0xFFFFu);
+    const uint32_t bb = 0xFFFFu - uint32_t(key & 0xFFFFu);
+    uint2 a, b;
+    a.x = pk;
+    a.y = (cnt ? jj : 0u) | ((cnt ? bb : 0u) << 16);
+    b.x = cnt;
+    b.y = nm;
+    P.out4[2 * c] = a;
+    P.out4[2 * c + 1] = b;
+}
+
+// Decoded candidate c: its event, local peak index, cell and event base.
+struct RzCand {
+    uint32_t e, pk, mask, k, p;
+    uint64_t eb;
+    const uint32_t *bo;
+};
+
+__device__ __forceinline__ RzCand rz_decode(const RzParams &P, uint64_t c)
+{
+    RzCand r;
+    const uint32_t nb = 1u << P.bucket_bits;
+    // event of candidate c: largest e with roff[e] <= c
+    uint32_t lo = 0, hi = P.n_events;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (P.roff[mid] <= c) lo = mid; else hi = mid;
+    }
+    r.e = uni(lo);
+    const uint32_t local = uni(uint32_t(c - P.roff[r.e]));
+    r.pk = P.cap ? uni(P.cand[c]) : local;
+    const uint64_t gp = uni64(P.poff[r.e] + r.pk);
+    const uint2 rec = P.peaks[gp];
+    const uint32_t cell = uni(rec.x);
+    r.mask = uni(rec.y & 0xFFFFu);
+    r.k = (cell >> P.log2phi) % P.n_qpt;
+    r.p = cell & (P.nphi - 1);
+    r.eb = uni64(min(P.offs[r.e], P.n_hits));
+    r.bo = P.bucket_off + size_t(r.e) * P.n_layers * (nb + 1);
+    return r;
+}
+
 __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
 {
     HOUGH_DYNAMIC_LDS(uint16_t, hist);       // [n_z0][64] when lds_ok
@@ -102,7 +217,6 @@ __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
         for (uint32_t i = lane; i < P.n_z0 * 64; i += 64) hist[i] = 0;
     __syncthreads();
     uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
-    const uint32_t nb = 1u << P.bucket_bits;
     for (;;) {
         // Work fetch without lane-divergent control flow: every lane executes
         // the atomic (only lane 0 adds 1) and lane 0's ticket is broadcast by
@@ -112,24 +226,11 @@ __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
         // an inner loop that never re-reads the counter).
         const uint64_t c = uni(atomicAdd(P.counter, lane == 0 ? 1u : 0u));
         if (c >= total) break;
-        // event of candidate c: largest e with roff[e] <= c
-        uint32_t lo = 0, hi = P.n_events;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (P.roff[mid] <= c) lo = mid; else hi = mid;
-        }
-        const uint32_t e = uni(lo);
-        const uint32_t local = uni(uint32_t(c - P.roff[e]));
-        const uint32_t pk = P.cap ? uni(P.cand[c]) : local;
-        const uint64_t gp = uni64(P.poff[e] + pk);
-        const uint2 rec = P.peaks[gp];
-        const uint32_t cell = uni(rec.x), mask = uni(rec.y & 0xFFFFu);
-        const uint32_t k = (cell >> P.log2phi) % P.n_qpt, p = cell & (P.nphi - 1);
-        const uint64_t eb = uni64(min(P.offs[e], P.n_hits));
-        const uint32_t *bo = P.bucket_off + size_t(e) * P.n_layers * (nb + 1);
+        const RzCand r = rz_decode(P, c);
+        const uint32_t k = r.k, p = r.p, mask = r.mask;
 
         uint32_t nm = 0;
-        for_members(P, eb, bo, k, p, mask, [&](uint32_t, uint32_t) { ++nm; });
+        for_members(P, r.eb, r.bo, k, p, mask, [&](uint32_t, uint32_t) { ++nm; });
 
         uint32_t best_c = 0, best_j = lane, best_b = 0;     // lane's best over its cot bins
         if (P.lds_ok && nm <= 65535u) {
@@ -137,83 +238,179 @@ __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
                 const uint32_t j = j0 + lane;
                 const bool jv = j < P.n_cot;
                 uint32_t bc = 0, bb = 0;
-                for_members(P, eb, bo, k, p, mask, [&](uint32_t h, uint32_t l) {
+                for_members(P, r.eb, r.bo, k, p, mask, [&](uint32_t h, uint32_t l) {
                     if (!jv) return;
                     const int64_t zl = int64_t(P.Z[(size_t(k) * P.n_layers + l) * P.n_cot + j]) + P.z0_lo;
-                    const int32_t b = z0_bin(P, P.z[eb + h], zl);
+                    const int32_t b = z0_bin(P, P.z[r.eb + h], zl);
                     if (b < 0) return;
                     const uint32_t idx = uint32_t(b) * 64 + lane;
                     const uint32_t cnt = uint32_t(hist[idx]) + 1;
                     hist[idx] = uint16_t(cnt);
                     if (cnt > bc || (cnt == bc && uint32_t(b) < bb)) { bc = cnt; bb = uint32_t(b); }
                 });
-                for_members(P, eb, bo, k, p, mask, [&](uint32_t h, uint32_t l) {
+                for_members(P, r.eb, r.bo, k, p, mask, [&](uint32_t h, uint32_t l) {
                     if (!jv) return;
                     const int64_t zl = int64_t(P.Z[(size_t(k) * P.n_layers + l) * P.n_cot + j]) + P.z0_lo;
-                    const int32_t b = z0_bin(P, P.z[eb + h], zl);
+                    const int32_t b = z0_bin(P, P.z[r.eb + h], zl);
                     if (b >= 0) hist[uint32_t(b) * 64 + lane] = 0;
                 });
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
             }
         } else {
-            // slow path: one cot bin at a time, lanes stride over the members
-            for (uint32_t j = 0; j < P.n_cot; ++j) {
-                for (int pass = 0; pass < 3; ++pass) {
-                    uint32_t seen = 0, bc = 0, bb = 0;
-                    for_members(P, eb, bo, k, p, mask, [&](uint32_t h, uint32_t l) {
-                        if ((seen++ & 63u) != lane) return;
-                        const int64_t zl = int64_t(P.Z[(size_t(k) * P.n_layers + l) * P.n_cot + j]) + P.z0_lo;
-                        const int32_t b = z0_bin(P, P.z[eb + h], zl);
-                        if (b < 0) return;
-                        if (pass == 0) {
-                            atomicAdd(&g[b], 1u);
-                        } else if (pass == 1) {
-                            const uint32_t cnt = __atomic_load_n(&g[b], __ATOMIC_RELAXED);
-                            if (cnt > bc || (cnt == bc && uint32_t(b) < bb)) { bc = cnt; bb = uint32_t(b); }
-                        } else {
-                            g[b] = 0;
-                        }
-                    });
-                    // every lane's updates of this pass are complete and
-                    // visible before any lane starts the next pass
-                    __threadfence();
-                    __syncthreads();
-                    if (pass == 1) {
-                        // wave argmax of (count desc, bin asc) for this cot bin
-                        uint64_t key = (uint64_t(bc) << 32) | (0xFFFFFFFFu - bb);
-                        for (int off = 32; off > 0; off >>= 1) {
-                            const uint64_t o = __shfl_xor(key, off, 64);
-                            key = o > key ? o : key;
-                        }
-                        const uint32_t cc = uint32_t(key >> 32), b = 0xFFFFFFFFu - uint32_t(key);
-                        if (cc > best_c) { best_c = cc; best_j = j; best_b = cc ? b : 0; }
-                    }
+            rz_slow(P, r.eb, r.bo, k, p, mask, g, lane, best_c, best_j, best_b);
+            if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
+        }
+        rz_finish(P, c, r.pk, nm, best_c, best_j, best_b);
+    }
+}
+
+// LDS layout of the fast kernel, in dwords.
+__host__ __device__ inline uint32_t rz_fast_lds_dwords(uint32_t hw, uint32_t mcap)
+{
+    return hw * 64 + 96 + 32 + mcap + (mcap + 3) / 4;
+}
+
+template <int BITS>
+__global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
+{
+    constexpr uint32_t PACK = 32 / BITS;           // counters per dword
+    constexpr uint32_t PSH = BITS == 8 ? 2 : 1;    // log2(PACK)
+    constexpr uint32_t FIELD = (1u << BITS) - 1u;
+    HOUGH_DYNAMIC_LDS(uint32_t, lds);
+    const uint32_t lane = threadIdx.x;
+    uint32_t *hist = lds;                            // [hw][64] lane-private packed counters
+    uint32_t *lay = hist + P.hw * 64;                // [5][16] per-layer windows
+    uint32_t *loff = lay + 96;                       // [L + 1] member offsets per layer
+    int32_t *mz = reinterpret_cast<int32_t *>(loff + 32);    // [mcap] member z
+    uint8_t *ml = reinterpret_cast<uint8_t *>(mz + P.mcap);  // [mcap] member layer
+    const uint32_t lim = min(P.mcap, FIELD);
+    const uint32_t nb = 1u << P.bucket_bits, bsh = 32 - P.bucket_bits;
+    const uint32_t nl = P.n_layers;
+    const uint32_t span = uint32_t(P.span);
+    const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
+    for (uint32_t i = lane; i < P.hw * 64; i += 64) hist[i] = 0;
+    __syncthreads();
+    uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
+    for (;;) {
+        const uint64_t c = uni(atomicAdd(P.counter, lane == 0 ? 1u : 0u));   // see k_rz_vote
+        if (c >= total) break;
+        const RzCand r = rz_decode(P, c);
+        const uint32_t k = r.k, p = r.p;
+
+        // 1a. lane l < L: the azimuth-bucket window of layer l (one or two
+        // ranges of the (layer, bucket)-sorted hits, two when it wraps)
+        uint32_t len1 = 0, len2 = 0, hs1 = 0, hs2 = 0, o = 0;
+        if (lane < nl && ((r.mask >> lane) & 1u)) {
+            const size_t ti = size_t(lane) * P.rows + k;
+            if (P.V[ti]) {
+                o = P.O[ti];
+                const uint32_t start = o + (p << P.shift);
+                const uint32_t b0 = start >> bsh;
+                const uint64_t W = uint64_t(1) << P.shift, BW = uint64_t(1) << bsh;
+                const uint32_t nbk = min(uint32_t(((uint64_t(start) & (BW - 1)) + W - 1) / BW + 1), nb);
+                const uint32_t *bl = r.bo + size_t(lane) * (nb + 1);
+                const uint32_t e1 = b0 + nbk;
+                hs1 = bl[b0];
+                if (e1 <= nb) {
+                    len1 = bl[e1] - hs1;
+                } else {
+                    len1 = bl[nb] - hs1;
+                    hs2 = bl[0];
+                    len2 = bl[e1 - nb] - hs2;
                 }
             }
+        }
+        // 1b. exclusive prefix of window lengths across the layer lanes
+        const uint32_t len = len1 + len2;
+        uint32_t incl = len;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            incl += lane >= d ? y : 0u;
+        }
+        const uint32_t T = uni(__shfl(incl, 63, 64));
+        if (lane < 16) {
+            lay[lane] = incl - len;
+            lay[16 + lane] = len1;
+            lay[32 + lane] = hs1;
+            lay[48 + lane] = hs2;
+            lay[64 + lane] = o;
+        }
+        __syncthreads();
+        // 1c. one pass over all scanned hits, ballot-compacting the members
+        // (their order is layer, then hit, so each layer's members are a run)
+        uint32_t nm = 0;
+        for (uint32_t g0 = 0; g0 < T; g0 += 64) {
+            const uint32_t gi = g0 + lane;
+            bool is_m = false;
+            int32_t zv = 0;
+            uint32_t ls = 0;
+            if (gi < T) {
+                for (uint32_t q = 0; q < nl; ++q) ls = lay[q] <= gi ? q : ls;
+                const uint32_t local = gi - lay[ls];
+                const uint32_t l1 = lay[16 + ls];
+                const uint32_t h = local < l1 ? lay[32 + ls] + local : lay[48 + ls] + (local - l1);
+                const uint32_t ph = P.phi[r.eb + h];
+                is_m = ((ph - lay[64 + ls]) >> P.shift) == p;
+                if (is_m) zv = P.z[r.eb + h];
+            }
+            const uint64_t bal = __ballot(is_m);
+            const uint32_t pos = nm + __popcll(bal & ((1ull << lane) - 1ull));
+            if (is_m && pos < lim) {
+                mz[pos] = zv;
+                ml[pos] = uint8_t(ls);
+            }
+            nm += __popcll(bal);
+        }
+        __syncthreads();
+
+        uint32_t best_c = 0, best_j = lane, best_b = 0;
+        if (nm <= lim) {
+            // loff[l] = first member whose layer is >= l (members sorted by layer)
+            if (lane <= nl) {
+                uint32_t a = 0, b = nm;
+                while (a < b) {
+                    const uint32_t mid = (a + b) >> 1;
+                    if (ml[mid] < lane) a = mid + 1; else b = mid;
+                }
+                loff[lane] = a;
+            }
+            __syncthreads();
+            for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 64) {
+                const uint32_t j = j0 + lane;
+                const bool jv = j < P.n_cot;
+                const uint32_t jj = jv ? j : P.n_cot - 1;
+                uint32_t bc = 0, bb = 0;
+                for (uint32_t l = 0; l < nl; ++l) {
+                    const uint32_t m0 = loff[l], m1 = loff[l + 1];
+                    if (m0 == m1) continue;
+                    const uint32_t zl = uint32_t(P.Zl[(size_t(k) * nl + l) * P.n_cot + jj]);
+                    for (uint32_t m = m0; m < m1; ++m) {
+                        const uint32_t u = uint32_t(mz[m]) - zl;
+                        const bool ok = jv && u < span;
+                        const uint32_t b = min(binmagic_apply(u, P.bm, P.bs), P.n_z0 - 1);
+                        const uint32_t sh = (b & (PACK - 1)) * BITS;
+                        const uint32_t old = atomicAdd(&hist[(b >> PSH) * 64 + lane], ok ? (1u << sh) : 0u);
+                        const uint32_t cnt = ((old >> sh) & FIELD) + 1u;
+                        const bool better = ok && (cnt > bc || (cnt == bc && b < bb));
+                        bc = better ? cnt : bc;
+                        bb = better ? b : bb;
+                    }
+                }
+                // clear all counters, 16 bytes per lane per store; a store
+                // covers other lanes' columns, so every lane's counting must
+                // be finished first and the clear finished before the next
+                // cot bins are counted
+                __syncthreads();
+                uint4 *h4 = reinterpret_cast<uint4 *>(hist);
+                for (uint32_t i = lane; i < P.hw * 16; i += 64) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+                __syncthreads();
+                if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
+            }
+        } else {
+            rz_slow(P, r.eb, r.bo, k, p, r.mask, g, lane, best_c, best_j, best_b);
             if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
-            else if (best_c == 0) { best_j = 0; best_b = 0; }
         }
-        // wave argmax of (count desc, cot asc, z0 asc)
-        uint64_t key = (uint64_t(best_c) << 32) | (uint64_t(0xFFFFu - (best_j & 0xFFFFu)) << 16) |
-                       (0xFFFFu - (best_b & 0xFFFFu));
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint64_t o = __shfl_xor(key, off, 64);
-            key = o > key ? o : key;
-        }
-        // key is wave-uniform after the butterfly: every lane stores the same
-        // record to the same address (no divergent branch at the loop tail)
-        {
-            const uint32_t cnt = uint32_t(key >> 32);
-            const uint32_t jj = 0xFFFFu - uint32_t((key >> 16) & 0xFFFFu);
-            const uint32_t bb = 0xFFFFu - uint32_t(key & 0xFFFFu);
-            uint2 a, b;
-            a.x = pk;
-            a.y = (cnt ? jj : 0u) | ((cnt ? bb : 0u) << 16);
-            b.x = cnt;
-            b.y = nm;
-            P.out4[2 * c] = a;
-            P.out4[2 * c + 1] = b;
-        }
+        rz_finish(P, c, r.pk, nm, best_c, best_j, best_b);
     }
 }
 
@@ -283,14 +480,9 @@ k_rz_select(const uint2 *__restrict__ peaks, uint64_t peak_capacity, const uint6
     }
 }
 
-__global__ void k_copy_u64(const uint64_t *__restrict__ a, uint64_t *__restrict__ b, uint64_t n)
-{
-    for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
-}
-
 uint32_t rz_blocks(const hough_ctx *c)
 {
-    const uint32_t w = c->tun.rz_waves_per_cu ? c->tun.rz_waves_per_cu : 4;
+    const uint32_t w = c->tun.rz_waves_per_cu ? c->tun.rz_waves_per_cu : 8;
     return uint32_t(c->n_cu) * w;
 }
 
@@ -329,6 +521,7 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     P.O = c->d_O;
     P.V = c->d_V;
     P.Z = c->d_Z;
+    P.Zl = c->d_Zl;
     P.peaks = reinterpret_cast<const uint2 *>(peaks);
     P.peak_capacity = peak_capacity;
     P.poff = poff;
@@ -353,10 +546,34 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     P.span = uint64_t(int64_t(g.z0_hi_um) - int64_t(g.z0_lo_um));
     P.use32 = P.span * g.n_z0 < (uint64_t(1) << 32);
     P.fd = make_fastdiv32(P.use32 ? uint32_t(P.span) : 1u);
+    P.bm = c->rz_magic_m;
+    P.bs = c->rz_magic_s;
+    const uint32_t blocks = rz_blocks(c);
+    // counter width: 8 bits when a cell's members (about hits / n_phi per
+    // event) stay well below 255; candidates that exceed it use the slow path
+    const double per_cell = double(h->n_hits) / double(std::max<uint32_t>(E, 1)) / double(g.n_phi);
+    uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 8u : 16u);
+    const uint32_t mcap = bits == 8 ? 256u : 1024u;
+    const uint32_t hw = (g.n_z0 + (32 / bits) - 1) / (32 / bits);
+    const size_t fast_lds = size_t(rz_fast_lds_dwords(hw, mcap)) * 4;
+    if (c->rz_fast && !c->tun.rz_slow_path && fast_lds <= c->max_lds) {
+        P.hw = hw;
+        P.mcap = mcap;
+        P.lds_ok = 0;
+        prof_begin(c, "rz_vote", s, &t);
+        if (bits == 8)
+            hipLaunchKernelGGL(k_rz_vote_fast<8>, dim3(blocks), dim3(64), fast_lds, s, P);
+        else
+            hipLaunchKernelGGL(k_rz_vote_fast<16>, dim3(blocks), dim3(64), fast_lds, s, P);
+        prof_end(c, s, &t);
+        return hipGetLastError();
+    }
     const size_t lds = size_t(g.n_z0) * 64 * sizeof(uint16_t);
     P.lds_ok = lds <= c->max_lds && !c->tun.rz_slow_path;
+    P.hw = 0;
+    P.mcap = 0;
     prof_begin(c, "rz_vote", s, &t);
-    hipLaunchKernelGGL(k_rz_vote, dim3(rz_blocks(c)), dim3(64), P.lds_ok ? lds : 0, s, P);
+    hipLaunchKernelGGL(k_rz_vote, dim3(blocks), dim3(64), P.lds_ok ? lds : 0, s, P);
     prof_end(c, s, &t);
     return hipGetLastError();
 }

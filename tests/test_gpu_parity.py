@@ -215,6 +215,22 @@ def test_peak_and_rz_capacity_overflow(H):
     assert seen >= 1
 
 
+@pytest.mark.parametrize("tuning,kw", [
+    (dict(rz_counter_bits=8), {}),
+    (dict(rz_counter_bits=16), {}),
+    (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),      # > 255 members: slow path
+    (dict(rz_counter_bits=16), dict(n_phi=2, n_qpt=4, n_cot=9)),      # > 1024 members: slow path
+    (None, dict(z0_lo_um=-2147483000, z0_hi_um=2147483000, n_z0=64)),  # general kernel
+])
+def test_rz_kernel_variants(H, tuning, kw):
+    spec = small_spec(**kw)
+    batch = ragged_batch()
+    res = run_gpu(H, spec, batch, tuning=tuning)
+    tab = oracle.Tables(spec)
+    for e in range(batch.n_events):
+        check_event(H, tab, res, batch, e, rz=True)
+
+
 def test_rz_candidate_cap_selection(H):
     spec = small_spec(rz_max_candidates=37)
     batch = ragged_batch()

@@ -99,3 +99,42 @@ int main() {
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-I",
                            os.path.join(ROOT, "paper_1310_7556_amd", "csrc"), str(src), "-o", str(exe)])
     subprocess.check_call([str(exe)])
+
+
+def test_binmagic_exact(tmp_path):
+    src = tmp_path / "b.cpp"
+    src.write_text(r'''
+#include "fastdiv.h"
+#include <cstdio>
+#include <random>
+int main() {
+    std::mt19937_64 rng(11);
+    struct C { uint64_t span; uint32_t n; };
+    const C cs[] = {{400000, 256}, {1, 1}, {3, 2}, {1000, 7}, {65535, 65535}, {4000000, 3},
+                    {2000000001ull, 256}, {4294967295ull, 1}, {123457, 65535}};
+    int tested = 0;
+    for (C c : cs) {
+        hough::BinMagic b = hough::make_binmagic(c.span, c.n);
+        if (!b.ok) continue;
+        tested++;
+        auto check = [&](uint64_t u) {
+            const uint64_t want = (unsigned __int128)u * c.n / c.span;
+            if (hough::binmagic_apply(uint32_t(u), b.m, b.s) != want) { printf("bad %llu %llu %u\n",
+                (unsigned long long)u, (unsigned long long)c.span, c.n); return false; }
+            return true;
+        };
+        if (c.span <= 5000000) { for (uint64_t u = 0; u < c.span; ++u) if (!check(u)) return 1; }
+        else for (int i = 0; i < 2000000; ++i) if (!check(rng() % c.span)) return 1;
+        for (uint64_t k = 0; k <= c.n; ++k) {          // bin edges and their neighbours
+            uint64_t e = ((unsigned __int128)k * c.span + c.n - 1) / c.n;
+            for (int64_t d = -1; d <= 1; ++d) { int64_t u = int64_t(e) + d; if (u >= 0 && uint64_t(u) < c.span && !check(u)) return 1; }
+            if (k > 4096) break;
+        }
+    }
+    return tested >= 4 ? 0 : 2;   // 400000/256, 3/2, 1000/7, 4e6/3 admit a 32-bit multiplier
+}
+''')
+    exe = tmp_path / "b"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I",
+                           os.path.join(ROOT, "paper_1310_7556_amd", "csrc"), str(src), "-o", str(exe)])
+    subprocess.check_call([str(exe)])
