@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serving", action="store_true", help="also run the serving sweep")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: events are independent, so more GPUs would "
@@ -241,7 +241,7 @@ def main():
         log("c4 batched vs plain ...")
         res["batched"] = bench_batched(H, torch)
         log(f"c4: graph {res['batched']['graph_ms']} ms, plain {res['batched']['plain_ms']} ms")
-    if args.serving:
+    if not args.no_serving:
         from paper_1310_7556_amd import serve
         log("c5 serving sweep ...")
         res["serving"] = serve.bench_serving(H, torch, log=log)

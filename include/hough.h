@@ -207,6 +207,21 @@ int hough_graph_capture(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc,
 int hough_graph_launch(hough_graph *graph, void *stream);
 void hough_graph_destroy(hough_graph *graph);
 
+/* ---- serving support ---------------------------------------------------- */
+
+/* Micro-batch assembly for the serving loop: copies n events out of a
+ * device-resident source SoA into one contiguous destination SoA.  Event i
+ * occupies source hits [src_off[i], src_off[i] + len[i]) and lands at
+ * destination hits [dst_off[i], dst_off[i] + len[i]); dst_off has n + 1
+ * entries and dst_off[n] is the destination's hit count, so dst_off is
+ * directly usable as the destination's event_offsets.  src_off, len and
+ * dst_off are device arrays; the caller guarantees every range lies inside
+ * its buffer.  z pointers may both be NULL.  Asynchronous on `stream`. */
+int hough_gather_events(const uint8_t *src_layer, const uint32_t *src_phi, const int32_t *src_z,
+                        const uint64_t *src_off, const uint64_t *len, const uint64_t *dst_off,
+                        uint32_t n, uint8_t *dst_layer, uint32_t *dst_phi, int32_t *dst_z,
+                        void *stream);
+
 /* ---- helpers (not on the hot path) ------------------------------------ */
 
 /* HOUGH_OK if the spec is valid, else HOUGH_EINVAL.  Host only. */

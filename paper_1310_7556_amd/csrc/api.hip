@@ -361,6 +361,19 @@ void hough_graph_destroy(hough_graph *graph)
     delete graph;
 }
 
+int hough_gather_events(const uint8_t *src_layer, const uint32_t *src_phi, const int32_t *src_z,
+                        const uint64_t *src_off, const uint64_t *len, const uint64_t *dst_off,
+                        uint32_t n, uint8_t *dst_layer, uint32_t *dst_phi, int32_t *dst_z,
+                        void *stream)
+{
+    if (n && (!src_layer || !src_phi || !src_off || !len || !dst_off || !dst_layer || !dst_phi))
+        return HOUGH_EINVAL;
+    if ((src_z == nullptr) != (dst_z == nullptr)) return HOUGH_EINVAL;
+    const hipError_t e = launch_gather_events(src_layer, src_phi, src_z, src_off, len, dst_off, n, dst_layer,
+                                              dst_phi, dst_z, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
 int hough_set_tuning(hough_ctx *ctx, const hough_tuning *tuning)
 {
     if (!ctx || !tuning || !tuning_ok(ctx, *tuning)) return HOUGH_EINVAL;

@@ -104,6 +104,9 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
 hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
                      uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
                      uint64_t capacity, uint64_t *event_rz_offsets, hipStream_t s);
+hipError_t launch_gather_events(const uint8_t *sl, const uint32_t *sp, const int32_t *sz, const uint64_t *src_off,
+                                const uint64_t *len, const uint64_t *dst_off, uint32_t n, uint8_t *dl,
+                                uint32_t *dp, int32_t *dz, hipStream_t s);
 uint32_t vote_rows(const hough_ctx *c);
 uint32_t rz_blocks(const hough_ctx *c);
 uint64_t max_peak_tiles(const hough_ctx *c);

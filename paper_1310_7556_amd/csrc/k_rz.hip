@@ -64,6 +64,9 @@ struct RzParams {
     uint32_t mcap;                // fast path: member list capacity
 };
 
+// candidates taken per work-counter ticket by the fast kernel
+constexpr uint32_t kRzChunk = 8;
+
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint64_t uni64(uint64_t v)
@@ -292,8 +295,12 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
     __syncthreads();
     uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
     for (;;) {
-        const uint64_t c = uni(atomicAdd(P.counter, lane == 0 ? 1u : 0u));   // see k_rz_vote
-        if (c >= total) break;
+        // a chunk of consecutive candidates per ticket (one contended atomic
+        // per kRzChunk candidates); the fetch itself as in k_rz_vote
+        const uint64_t c0 = uni(atomicAdd(P.counter, lane == 0 ? kRzChunk : 0u));
+        if (c0 >= total) break;
+        const uint64_t c1 = min(c0 + kRzChunk, total);
+      for (uint64_t c = c0; c < c1; ++c) {
         const RzCand r = rz_decode(P, c);
         const uint32_t k = r.k, p = r.p;
 
@@ -365,37 +372,67 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
 
         uint32_t best_c = 0, best_j = lane, best_b = 0;
         if (nm <= lim) {
-            // loff[l] = first member whose layer is >= l (members sorted by layer)
-            if (lane <= nl) {
-                uint32_t a = 0, b = nm;
-                while (a < b) {
-                    const uint32_t mid = (a + b) >> 1;
-                    if (ml[mid] < lane) a = mid + 1; else b = mid;
-                }
-                loff[lane] = a;
-            }
-            __syncthreads();
+            const int32_t *zrow = P.Zl + size_t(k) * nl * P.n_cot;
+            // all layers' (Z + z0_lo) for this lane's cot bin: loaded for the
+            // next pass while the current one counts (one memory latency per
+            // candidate instead of one per pass)
+            uint32_t zr[kMaxLayers], zn[kMaxLayers];
+#pragma unroll
+            for (uint32_t l = 0; l < kMaxLayers; ++l)
+                zr[l] = l < nl ? uint32_t(zrow[size_t(l) * P.n_cot + min(lane, P.n_cot - 1)]) : 0u;
             for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 64) {
                 const uint32_t j = j0 + lane;
                 const bool jv = j < P.n_cot;
-                const uint32_t jj = jv ? j : P.n_cot - 1;
-                uint32_t bc = 0, bb = 0;
-                for (uint32_t l = 0; l < nl; ++l) {
-                    const uint32_t m0 = loff[l], m1 = loff[l + 1];
-                    if (m0 == m1) continue;
-                    const uint32_t zl = uint32_t(P.Zl[(size_t(k) * nl + l) * P.n_cot + jj]);
-                    for (uint32_t m = m0; m < m1; ++m) {
-                        const uint32_t u = uint32_t(mz[m]) - zl;
-                        const bool ok = jv && u < span;
-                        const uint32_t b = min(binmagic_apply(u, P.bm, P.bs), P.n_z0 - 1);
-                        const uint32_t sh = (b & (PACK - 1)) * BITS;
-                        const uint32_t old = atomicAdd(&hist[(b >> PSH) * 64 + lane], ok ? (1u << sh) : 0u);
-                        const uint32_t cnt = ((old >> sh) & FIELD) + 1u;
-                        const bool better = ok && (cnt > bc || (cnt == bc && b < bb));
-                        bc = better ? cnt : bc;
-                        bb = better ? b : bb;
-                    }
+                // lanes past the last cot bin count nothing (their span is 0)
+                const uint32_t lspan = jv ? span : 0u;
+                // running maximum of key = count << 16 | (0xFFFF - bin): the
+                // largest key has the largest count, ties to the smallest bin
+                uint32_t run = 0;
+                const uint32_t jn = min(j + 64, P.n_cot - 1);
+                const bool more = j0 + 64 < P.n_cot;
+#pragma unroll
+                for (uint32_t l = 0; l < kMaxLayers; ++l)
+                    zn[l] = (more && l < nl) ? uint32_t(zrow[size_t(l) * P.n_cot + jn]) : 0u;
+                // one member's vote, straight-line integer code: in-range
+                // test, bin, lane-private packed counter, running maximum
+                auto bin_of = [&](uint32_t zm, uint32_t zl, uint32_t &b, uint32_t &sh, uint32_t &inc) {
+                    const uint32_t u = zm - zl;
+                    const uint32_t ok = u < lspan ? 1u : 0u;
+                    b = min(__umulhi(u, P.bm) >> P.bs, P.n_z0 - 1);
+                    sh = (b & (PACK - 1)) * BITS;
+                    inc = ok << sh;
+                };
+                auto take = [&](uint32_t old, uint32_t b, uint32_t sh, uint32_t inc) {
+                    const uint32_t key = ((((old >> sh) & FIELD) + 1u) << 16) | (0xFFFFu - b);
+                    run = max(run, inc ? key : 0u);
+                };
+                // all members in one flat loop, four per step: one 16-byte
+                // LDS read gives four z, one 4-byte read their four layers
+                // (so (Z + z0_lo) is a register-indexed move), then four
+                // counter atomics in flight and four running-max updates
+                const uint4 *mz4 = reinterpret_cast<const uint4 *>(mz);
+                const uint32_t *ml4 = reinterpret_cast<const uint32_t *>(ml);
+                uint32_t m = 0;
+                for (; m + 4 <= nm; m += 4) {
+                    const uint4 zq = mz4[m >> 2];
+                    const uint32_t lq = uni(ml4[m >> 2]);
+                    const uint32_t zm[4] = {zq.x, zq.y, zq.z, zq.w};
+                    uint32_t b[4], sh[4], inc[4], old[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bin_of(zm[q], zr[(lq >> (8 * q)) & 0xFFu], b[q], sh[q], inc[q]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) old[q] = atomicAdd(&hist[(b[q] >> PSH) * 64 + lane], inc[q]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) take(old[q], b[q], sh[q], inc[q]);
                 }
+                for (; m < nm; ++m) {
+                    uint32_t b, sh, inc;
+                    bin_of(uint32_t(mz[m]), zr[uni(ml[m])], b, sh, inc);
+                    take(atomicAdd(&hist[(b >> PSH) * 64 + lane], inc), b, sh, inc);
+                }
+                const uint32_t bc = run >> 16, bb = 0xFFFFu - (run & 0xFFFFu);
+#pragma unroll
+                for (uint32_t l = 0; l < kMaxLayers; ++l) zr[l] = zn[l];
                 // clear all counters, 16 bytes per lane per store; a store
                 // covers other lanes' columns, so every lane's counting must
                 // be finished first and the clear finished before the next
@@ -411,6 +448,7 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
             if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
         }
         rz_finish(P, c, r.pk, nm, best_c, best_j, best_b);
+      }
     }
 }
 
@@ -553,8 +591,14 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     // event) stay well below 255; candidates that exceed it use the slow path
     const double per_cell = double(h->n_hits) / double(std::max<uint32_t>(E, 1)) / double(g.n_phi);
     uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 8u : 16u);
-    const uint32_t mcap = bits == 8 ? 256u : 1024u;
     const uint32_t hw = (g.n_z0 + (32 / bits) - 1) / (32 / bits);
+    // member list: 256 with 8-bit counters (their limit is 255), else as many
+    // as fit the LDS budget, up to 4096
+    uint32_t mcap = 256;
+    if (bits == 16) {
+        mcap = 4096;
+        while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;
+    }
     const size_t fast_lds = size_t(rz_fast_lds_dwords(hw, mcap)) * 4;
     if (c->rz_fast && !c->tun.rz_slow_path && fast_lds <= c->max_lds) {
         P.hw = hw;

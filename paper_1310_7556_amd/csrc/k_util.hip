@@ -44,6 +44,35 @@ k_scan_counts(const uint32_t *__restrict__ counts, uint64_t n, uint64_t *__restr
     }
 }
 
+// Copies event i's hits from [src_off[i], +len[i]) to [dst_off[i], +len[i]).
+// blockIdx.y strides over events, (blockIdx.x, threadIdx.x) over hits.
+__global__ void __launch_bounds__(256)
+k_gather_events(const uint8_t *__restrict__ sl, const uint32_t *__restrict__ sp, const int32_t *__restrict__ sz,
+                const uint64_t *__restrict__ src_off, const uint64_t *__restrict__ len,
+                const uint64_t *__restrict__ dst_off, uint32_t n, uint8_t *__restrict__ dl,
+                uint32_t *__restrict__ dp, int32_t *__restrict__ dz)
+{
+    for (uint32_t e = blockIdx.y; e < n; e += gridDim.y) {
+        const uint64_t s0 = src_off[e], d0 = dst_off[e], m = len[e];
+        for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
+             i += uint64_t(gridDim.x) * blockDim.x) {
+            dl[d0 + i] = sl[s0 + i];
+            dp[d0 + i] = sp[s0 + i];
+            if (sz) dz[d0 + i] = sz[s0 + i];
+        }
+    }
+}
+
+hipError_t launch_gather_events(const uint8_t *sl, const uint32_t *sp, const int32_t *sz, const uint64_t *src_off,
+                                const uint64_t *len, const uint64_t *dst_off, uint32_t n, uint8_t *dl,
+                                uint32_t *dp, int32_t *dz, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_events, dim3(64, std::min(n, 65535u)), dim3(256), 0, s, sl, sp, sz, src_off, len,
+                       dst_off, n, dl, dp, dz);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(hough_ctx *c, uint32_t *p, uint32_t v, size_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;

@@ -21,7 +21,7 @@ EXPORTED = [
     "hough_graph_capture", "hough_graph_launch", "hough_graph_destroy",
     "hough_check_spec", "hough_build_tables", "hough_set_tuning", "hough_get_tuning",
     "hough_set_profiling", "hough_kernel_times", "hough_kernel_times_reset",
-    "hough_strerror", "hough_last_error", "hough_device_cus",
+    "hough_strerror", "hough_last_error", "hough_device_cus", "hough_gather_events",
 ]
 
 PEAK_DTYPE = np.dtype([("cell", np.uint32), ("mask", np.uint16), ("popcount", np.uint16)])
@@ -89,6 +89,7 @@ def load_library():
         "hough_strerror": ([i32], C.c_char_p),
         "hough_last_error": ([P], C.c_char_p),
         "hough_device_cus": ([P], i32),
+        "hough_gather_events": ([P, P, P, P, P, P, u32, P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -338,6 +339,16 @@ class HoughContext:
     @property
     def n_cu(self):
         return self.lib.hough_device_cus(self._h)
+
+
+def gather_events(src, src_off, lens, dst_off, n, dst_layer, dst_phi, dst_z, stream=None):
+    """Assemble n events of `src` (DeviceHits) into contiguous destination
+    arrays (device tensors); src_off/lens/dst_off are device int64 tensors."""
+    lib = load_library()
+    rc = lib.hough_gather_events(_ptr(src.layer), _ptr(src.phi), _ptr(src.z) if dst_z is not None else None,
+                                 _ptr(src_off), _ptr(lens), _ptr(dst_off), n, _ptr(dst_layer),
+                                 _ptr(dst_phi), _ptr(dst_z), _stream(stream))
+    _check(rc, what="hough_gather_events")
 
 
 # ---- numpy views of device results ----------------------------------------

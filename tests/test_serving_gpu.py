@@ -1,0 +1,50 @@
+"""Serving on the GPU: every request completes, and a request's accumulator,
+peaks and rz records are identical whether it is served alone or inside a
+Poisson mix of concurrently running micro-batches (exact equality: the
+results are integers)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("staged", [True, False])
+def test_results_alone_equal_results_in_the_mix(staged):
+    import torch
+    from paper_1310_7556_amd import hough as H
+    from paper_1310_7556_amd.serve import (GpuBackend, Scheduler, WallClock, latency_stats,
+                                           make_requests, run_trace)
+    name = "c5_serving"
+    spec = synth.grid_spec(name)
+    pool = synth.gen_batch(name, 6)
+    sizes = np.diff(pool.offsets.astype(np.int64))
+    keep = [3, 40, 77, 119]
+    clock = WallClock()
+    max_hits = int(sizes.sum())
+    be = GpuBackend(H, torch, spec, pool, 3, 8, max_hits, clock, staged=staged, keep=keep)
+    arr = synth.arrival_times(name, 20000, 120)
+    reqs = make_requests(pool, 20000, 120, arr, lambda n: 1)
+    sched = Scheduler(3, 8, max_hits, 10**15)
+    be.start()
+    t0 = clock.now()
+    for r in reqs:
+        r.arrival += t0
+    run_trace(reqs, sched, be, clock)
+    st = latency_stats(reqs)
+    assert st["n"] == 120 and all(r.done >= r.arrival for r in reqs)
+    assert max(len(b) for b in [[r for r in reqs if r.admitted == t] for t in {r.admitted for r in reqs}]) > 1
+    assert set(be.kept) == set(keep)
+    for rid in keep:
+        e = reqs[rid].event
+        ctx = H.HoughContext(spec, max_events=1, max_hits=int(sizes[e]))
+        hits = H.DeviceHits.from_batch(pool.event(e))
+        acc = ctx.vote(hits)
+        pk, poff = ctx.peaks(acc, 1)
+        rz, roff = ctx.rz_refine(hits, pk, poff)
+        torch.cuda.synchronize()
+        acc_m, pk_m, rz_m = be.kept[rid]
+        np.testing.assert_array_equal(acc_m, H.acc_numpy(acc)[0])
+        np.testing.assert_array_equal(pk_m, H.peaks_numpy(pk, poff))
+        np.testing.assert_array_equal(rz_m, H.rz_numpy(rz, roff))
