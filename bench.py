@@ -33,6 +33,15 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # integer operations per rz (member, cot bin) vote: z - Z, - z0_lo, range
 # test, * n_z0, / span, histogram increment, running-maximum compare
 RZ_OPS_PER_VOTE = 7
+# Algorithmic HBM bytes of the vote kernels for n_hits hits and `cells`
+# accumulator cells: the per-hit scatter reads layer + phi (5 B) and writes
+# each uint16 cell once; the gap form splits that into a scan that reads
+# the hits and a tile kernel that writes the cells.
+VOTE_KERNEL_BYTES = {
+    "vote_lds": lambda n_hits, cells: 5 * n_hits + 2 * cells,
+    "vote_scan": lambda n_hits, cells: 5 * n_hits,
+    "vote_gaps": lambda n_hits, cells: 2 * cells,
+}
 
 
 def log(*a):
@@ -95,10 +104,7 @@ def bench_single(H, torch, steps, warmup):
                                work_per_launch=f"{rz_votes} member x cot votes x {RZ_OPS_PER_VOTE} int ops")
     else:
         t = kernel_avg_ms(times, dom) * 1e-3
-        if dom == "vote_lds":
-            byts = 5 * ev.n_hits + 2 * ctx.cells
-        else:
-            byts = 2 * ctx.cells
+        byts = VOTE_KERNEL_BYTES.get(dom, lambda n_hits, cells: 2 * cells)(ev.n_hits, ctx.cells)
         gbs = byts / t / 1e9
         out["roofline"] = dict(kernel=dom, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
                                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None)
@@ -140,9 +146,13 @@ def bench_batched(H, torch, reps=5):
         stream.synchronize()
         ctx.set_profiling(False)
         times = ctx.kernel_times()
-    t_vote = kernel_avg_ms(times, "vote_lds") * 1e-3
-    vote_bytes = 5 * batch.n_hits + 2 * E * ctx.cells
+    vk = "vote_gaps" if "vote_gaps" in times else "vote_lds"
+    t_vote = kernel_avg_ms(times, vk) * 1e-3
+    vote_bytes = VOTE_KERNEL_BYTES[vk](batch.n_hits, E * ctx.cells)
     gbs = vote_bytes / t_vote / 1e9
+    stage_bytes = 5 * batch.n_hits + 2 * E * ctx.cells
+    t_stage = sum(kernel_avg_ms(times, k) for k in ("vote_scan", "vote_gaps", "vote_lds", "bucket_layers")
+                  if k in times) * 1e-3
 
     # plain path: one event per launch, same kernels, same GPU
     import ctypes as C
@@ -186,9 +196,12 @@ def bench_batched(H, torch, reps=5):
         plain_ms=round(t_plain * 1e3, 3), plain_events_per_s=E / t_plain,
         speedup_vs_plain=round(t_plain / t_graph, 3),
         stage_ms={k: round(v[1] / v[0], 4) for k, v in times.items() if v[0]},
-        roofline=dict(kernel="vote_lds", bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
+        roofline=dict(kernel=vk, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None,
-                      bytes_per_launch=vote_bytes))
+                      bytes_per_launch=vote_bytes),
+        vote_stage=dict(kernels_ms=round(t_stage * 1e3, 4), bytes=stage_bytes,
+                        achieved_gbs=round(stage_bytes / t_stage / 1e9, 2),
+                        frac=round(stage_bytes / t_stage / 1e9 / HBM_PEAK_GBS, 5)))
 
 
 def cpu_baseline(spec, ev):

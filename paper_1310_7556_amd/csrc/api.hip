@@ -49,7 +49,7 @@ void free_all(hough_ctx *c)
 {
     void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
-                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist};
+                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : c->pending) {
@@ -80,7 +80,8 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.vote_wgs_per_cu > 32) return false;
     if (t.peak_rows > 4096) return false;
     if (t.rz_waves_per_cu > kMaxRzWavesPerCu) return false;
-    if (t.vote_algo > 2) return false;
+    if (t.vote_algo > 3) return false;
+    if (t.vote_algo == 3 && !hough::gap_vote_usable(c)) return false;
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16) return false;
     return true;
@@ -228,7 +229,8 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
               dev_alloc(&c->d_bucket_off, size_t(E) * L * nb) && dev_alloc(&c->d_order, E) &&
               dev_alloc(&c->d_counters, 64) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&
               dev_alloc(&c->d_tile_off, c->n_peak_tiles + 1) && dev_alloc(&c->d_cand, ncand) &&
-              dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh);
+              dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh) &&
+              dev_alloc(&c->d_gap_info, size_t(E) * L) && dev_alloc(&c->d_gap_list, H);
     if (!ok) {
         free_all(c);
         delete c;

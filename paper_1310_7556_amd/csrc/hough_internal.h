@@ -75,6 +75,8 @@ struct hough_ctx {
     uint32_t *d_cand = nullptr;        // [max_events * rz_max_candidates]
     uint32_t *d_cand_counts = nullptr; // [max_events]
     uint32_t *d_rz_hist = nullptr;     // [rz blocks][n_z0] zeroed uint32 (rz slow path)
+    uint4 *d_gap_info = nullptr;       // [max_events][L] gap vote: {mode, entries, list start, 0}
+    uint2 *d_gap_list = nullptr;       // [max_hits] gap vote: per-layer hit or gap lists
     uint64_t n_peak_tiles = 0;
 
     // profiling
@@ -108,6 +110,9 @@ hipError_t launch_gather_events(const uint8_t *sl, const uint32_t *sp, const int
                                 const uint64_t *len, const uint64_t *dst_off, uint32_t n, uint8_t *dl,
                                 uint32_t *dp, int32_t *dz, hipStream_t s);
 uint32_t vote_rows(const hough_ctx *c);
+hipError_t launch_vote_gaps(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
+uint32_t gap_rows(const hough_ctx *c);
+bool gap_vote_usable(const hough_ctx *c);
 uint32_t rz_blocks(const hough_ctx *c);
 uint64_t max_peak_tiles(const hough_ctx *c);
 

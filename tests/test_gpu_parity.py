@@ -153,6 +153,8 @@ def ragged_batch():
 
 
 @pytest.mark.parametrize("tuning", [None, dict(vote_rows=1), dict(vote_rows=4, vote_threads=64),
+                                    dict(vote_algo=1), dict(vote_algo=1, vote_rows=4, vote_threads=64),
+                                    dict(vote_algo=3, vote_rows=64, vote_threads=1024),
                                     dict(vote_algo=2), dict(peak_rows=1), dict(peak_rows=7),
                                     dict(rz_slow_path=1), dict(vote_threads=1024, vote_wgs_per_cu=1)])
 def test_ragged_batch_with_empty_events(H, tuning):
@@ -173,6 +175,45 @@ def test_degenerate_grids(H, kw):
                                  for b in [synth.gen_config("c1_single_100trk")]])
     res = run_gpu(H, spec, batch)
     check_event(H, oracle.Tables(spec), res, batch, 0, rz=True)
+
+
+def gap_layout_batch(n_phi):
+    """Events whose layers stress the gap form of the vote: every hit of a
+    layer in one azimuth bucket (one gap of almost a full turn), repeated
+    hits, hits on bucket edges and at 0 and 2^32 - 1, exactly n_phi/2 and
+    n_phi/2 + 1 hits in a layer (the sparse/dense switch), all gaps exactly
+    one bin wide (full rows) and all gaps one unit wider than a bin."""
+    W = 1 << (32 - int(math.log2(n_phi)))
+    rng = np.random.default_rng(11)
+    evs = []
+
+    def add(parts):
+        layer = np.concatenate([np.full(len(p), l, np.uint8) for l, p in parts])
+        phi = np.concatenate([np.asarray(p, np.uint64) % (1 << 32) for _, p in parts]).astype(np.uint32)
+        evs.append((layer, phi, np.zeros(len(phi), np.int32)))
+
+    add([(2, [5 * W + 3] * (n_phi // 2) + [6 * W - 1] * 20 + [0, (1 << 32) - 1, W, W - 1])])
+    add([(0, [k * W for k in range(n_phi) if not (n_phi // 8 <= k < n_phi // 4)] +
+          [k * W + W // 2 for k in range(n_phi)])])
+    add([(1, rng.integers(0, 1 << 32, n_phi // 2)), (3, rng.integers(0, 1 << 32, n_phi // 2 + 1)),
+         (9, [12345])])
+    add([(4, [k * W for k in range(n_phi)]), (5, [k * (W + 1) for k in range(n_phi - 1)]),
+         (6, [k * W + W - 1 for k in range(n_phi)] * 2)])
+    add([(l, rng.integers(0, 1 << 32, 3 * n_phi)) for l in range(10)])
+    return synth.concat_events(evs)
+
+
+@pytest.mark.parametrize("kw", [dict(n_phi=64, n_qpt=16), dict(n_phi=1024, n_qpt=8),
+                                dict(n_phi=64, n_qpt=8, n_d0=8, d0_lo_mm=-120.0, d0_hi_mm=120.0, n_z0=0)])
+def test_gap_vote_layer_layouts(H, kw):
+    spec = small_spec(**kw)
+    batch = gap_layout_batch(spec["n_phi"])
+    tab = oracle.Tables(spec)
+    gap = run_gpu(H, spec, batch, rz=False)
+    per_hit = run_gpu(H, spec, batch, tuning=dict(vote_algo=1), rz=False)
+    np.testing.assert_array_equal(H.acc_numpy(gap["acc"]), H.acc_numpy(per_hit["acc"]))
+    for e in range(batch.n_events):
+        check_event(H, tab, gap, batch, e)
 
 
 def test_displaced_small_grid_unreachable_rows(H):
@@ -317,5 +358,7 @@ def test_limits_and_bad_arguments_raise(H):
         ctx.vote(hits)
     with pytest.raises(H.HoughError):
         ctx.set_tuning(vote_rows=3)
+    with pytest.raises(H.HoughError):
+        ctx.set_tuning(vote_algo=4)
     with pytest.raises(H.HoughError):
         H.HoughContext(dict(spec, n_phi=48))
