@@ -35,10 +35,12 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 RZ_OPS_PER_VOTE = 7
 # Algorithmic HBM bytes of the vote kernels for n_hits hits and `cells`
 # accumulator cells: the per-hit scatter reads layer + phi (5 B) and writes
-# each uint16 cell once; the gap form splits that into a scan that reads
-# the hits and a tile kernel that writes the cells.
+# each uint16 cell once; the bucket-bounds and gap forms split that into a
+# scan that reads the hits and a tile kernel that writes the cells.
 VOTE_KERNEL_BYTES = {
     "vote_lds": lambda n_hits, cells: 5 * n_hits + 2 * cells,
+    "vote_bounds": lambda n_hits, cells: 5 * n_hits,
+    "vote_direct": lambda n_hits, cells: 2 * cells,
     "vote_scan": lambda n_hits, cells: 5 * n_hits,
     "vote_gaps": lambda n_hits, cells: 2 * cells,
 }
@@ -146,12 +148,13 @@ def bench_batched(H, torch, reps=5):
         stream.synchronize()
         ctx.set_profiling(False)
         times = ctx.kernel_times()
-    vk = "vote_gaps" if "vote_gaps" in times else "vote_lds"
+    vk = next(k for k in ("vote_direct", "vote_gaps", "vote_lds") if k in times)
     t_vote = kernel_avg_ms(times, vk) * 1e-3
     vote_bytes = VOTE_KERNEL_BYTES[vk](batch.n_hits, E * ctx.cells)
     gbs = vote_bytes / t_vote / 1e9
     stage_bytes = 5 * batch.n_hits + 2 * E * ctx.cells
-    t_stage = sum(kernel_avg_ms(times, k) for k in ("vote_scan", "vote_gaps", "vote_lds", "bucket_layers")
+    t_stage = sum(kernel_avg_ms(times, k) for k in ("vote_bounds", "vote_direct", "vote_scan", "vote_gaps",
+                                                     "vote_lds", "bucket_layers")
                   if k in times) * 1e-3
 
     # plain path: one event per launch, same kernels, same GPU

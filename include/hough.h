@@ -128,7 +128,8 @@ typedef struct {
     uint32_t vote_wgs_per_cu;       /* persistent vote grid: workgroups per compute unit */
     uint32_t peak_rows;             /* accumulator rows per peak-finding tile */
     uint32_t rz_waves_per_cu;       /* persistent rz grid: waves per compute unit */
-    uint32_t vote_algo;             /* 0 = default, 1 = LDS atomic scatter, 2 = global atomics */
+    uint32_t vote_algo;             /* 0 = default (4), 1 = per-hit LDS atomics, 2 = global atomics,
+                                       3 = hit-gap lists, 4 = bucket bounds (direct occupancy) */
     uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
     uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 8 or 16 */
 } hough_tuning;
@@ -153,8 +154,8 @@ void hough_destroy(hough_ctx *ctx);
  * Discussion's A[B[i]] += 1 in its layer-mask form).  For every event e,
  * every hit h of e with layer l < n_layers and every reachable row (d, k):
  *     acc[e][d][k][(phi_h - O[l][d][k]) >> (32 - log2 n_phi)] |= 1 << l.
- * acc: device, n_events * n_d0 * n_qpt * n_phi uint16, fully overwritten
- * (no need to clear it).  Requires n_events <= max_events and
+ * acc: device, n_events * n_d0 * n_qpt * n_phi uint16, 4-byte aligned
+ * (HOUGH_EINVAL otherwise), fully overwritten (no need to clear it).  Requires n_events <= max_events and
  * n_hits <= max_hits (HOUGH_ELIMIT).  hits->z_um is not read. */
 int hough_vote(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, void *stream);
 

@@ -49,7 +49,8 @@ void free_all(hough_ctx *c)
 {
     void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
-                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list};
+                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list,
+                    c->d_scan_part, c->d_scan_off, c->d_dir_tab};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : c->pending) {
@@ -80,8 +81,9 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.vote_wgs_per_cu > 32) return false;
     if (t.peak_rows > 4096) return false;
     if (t.rz_waves_per_cu > kMaxRzWavesPerCu) return false;
-    if (t.vote_algo > 3) return false;
+    if (t.vote_algo > 4) return false;
     if (t.vote_algo == 3 && !hough::gap_vote_usable(c)) return false;
+    if (t.vote_algo == 4 && !hough::direct_vote_usable(c)) return false;
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16) return false;
     return true;
@@ -179,6 +181,7 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = std::min<size_t>(size_t(lds) - 512, 65536);   // headroom for static LDS
+        c->max_lds_direct = c->max_lds;
     while ((1u << c->log2_phi) < spec->n_phi) ++c->log2_phi;
     c->shift = 32 - c->log2_phi;
     c->rows = spec->n_d0 * spec->n_qpt;
@@ -218,10 +221,11 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     const uint32_t E = limits->max_events;
     const uint32_t L = spec->n_layers;
     c->n_peak_tiles = std::max<uint64_t>(uint64_t(E) * c->rows, E);
+    c->scan_blocks_max = scan_blocks(c->n_peak_tiles);
     const size_t nb = rz ? (size_t(1) << c->bucket_bits) + 1 : 0;
     const size_t ncand = rz ? size_t(E) * spec->rz_max_candidates : 0;
     const size_t rzh = rz ? size_t(c->n_cu) * kMaxRzWavesPerCu * spec->n_z0 : 0;
-    bool ok = dev_alloc(&c->d_O, nOV) && dev_alloc(&c->d_V, nOV) && dev_alloc(&c->d_Z, Z.size()) &&
+    bool ok = dev_alloc(&c->d_O, nOV + kOPad) && dev_alloc(&c->d_V, nOV) && dev_alloc(&c->d_Z, Z.size()) &&
               dev_alloc(&c->d_Zl, Zl.size()) &&
               dev_alloc(&c->d_phi_a, H) && dev_alloc(&c->d_z_a, rz ? H : 0) &&
               dev_alloc(&c->d_phi_b, rz ? H : 0) && dev_alloc(&c->d_z_b, rz ? H : 0) &&
@@ -230,13 +234,16 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
               dev_alloc(&c->d_counters, 64) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&
               dev_alloc(&c->d_tile_off, c->n_peak_tiles + 1) && dev_alloc(&c->d_cand, ncand) &&
               dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh) &&
-              dev_alloc(&c->d_gap_info, size_t(E) * L) && dev_alloc(&c->d_gap_list, H);
+              dev_alloc(&c->d_gap_info, size_t(E) * L) && dev_alloc(&c->d_gap_list, H) &&
+              dev_alloc(&c->d_scan_part, c->scan_blocks_max) && dev_alloc(&c->d_scan_off, c->scan_blocks_max + 1) &&
+              dev_alloc(&c->d_dir_tab, size_t(E) * L * spec->n_phi);
     if (!ok) {
         free_all(c);
         delete c;
         return HOUGH_ENOMEM;
     }
-    hipError_t err = hipMemcpy(c->d_O, O.data(), nOV * 4, hipMemcpyHostToDevice);
+    hipError_t err = hipMemset(c->d_O, 0, (nOV + kOPad) * 4);
+    if (err == hipSuccess) err = hipMemcpy(c->d_O, O.data(), nOV * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemcpy(c->d_V, V.data(), nOV, hipMemcpyHostToDevice);
     if (err == hipSuccess && rz) err = hipMemcpy(c->d_Z, Z.data(), Z.size() * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess && !Zl.empty())
@@ -264,6 +271,7 @@ void hough_destroy(hough_ctx *ctx)
 int hough_vote(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, void *stream)
 {
     if (!ctx || !hits_ok(ctx, hits, false) || (hits->n_events && !acc)) return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(acc) & 3) return HOUGH_EINVAL;
     if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
     DeviceGuard guard(ctx->device);
     const hipError_t e = launch_vote(ctx, hits, acc, static_cast<hipStream_t>(stream));

@@ -23,6 +23,10 @@ namespace hough {
 // log2(n_phi) + 2 bits, at most 12 (4096 buckets per layer).
 constexpr uint32_t kMaxBucketBits = 12;
 
+// The offset table is followed by this many zero entries, so a kernel may
+// read a whole tile's worth of offsets past the last row.
+constexpr size_t kOPad = 64;
+
 struct KernelTimer {
     const char *name;
     hipEvent_t start, stop;
@@ -51,7 +55,7 @@ struct hough_ctx {
     uint32_t bucket_bits = 0;    // rz member search buckets (0 when no rz)
 
     // tables (device)
-    uint32_t *d_O = nullptr;     // [L][rows]
+    uint32_t *d_O = nullptr;     // [L][rows] + kOPad zero entries
     uint8_t *d_V = nullptr;      // [L][rows]
     int32_t *d_Z = nullptr;      // [n_qpt][L][n_cot]
     int32_t *d_Zl = nullptr;     // [n_qpt][L][n_cot] = Z + z0_lo, when rz_fast
@@ -77,6 +81,11 @@ struct hough_ctx {
     uint32_t *d_rz_hist = nullptr;     // [rz blocks][n_z0] zeroed uint32 (rz slow path)
     uint4 *d_gap_info = nullptr;       // [max_events][L] gap vote: {mode, entries, list start, 0}
     uint2 *d_gap_list = nullptr;       // [max_hits] gap vote: per-layer hit or gap lists
+    uint64_t *d_scan_part = nullptr;   // [scan_blocks_max] block sums of a multi-block scan
+    uint64_t *d_scan_off = nullptr;    // [scan_blocks_max + 1] their exclusive prefix
+    uint64_t scan_blocks_max = 0;
+    uint2 *d_dir_tab = nullptr;        // [max_events][L][n_phi] direct vote: per-bucket {lo, span}
+    size_t max_lds_direct = 65536;     // LDS budget of the direct vote's table staging
     uint64_t n_peak_tiles = 0;
 
     // profiling
@@ -111,12 +120,16 @@ hipError_t launch_gather_events(const uint8_t *sl, const uint32_t *sp, const int
                                 uint32_t *dp, int32_t *dz, hipStream_t s);
 uint32_t vote_rows(const hough_ctx *c);
 hipError_t launch_vote_gaps(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
+hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
+bool direct_vote_usable(const hough_ctx *c);
 uint32_t gap_rows(const hough_ctx *c);
 bool gap_vote_usable(const hough_ctx *c);
 uint32_t rz_blocks(const hough_ctx *c);
 uint64_t max_peak_tiles(const hough_ctx *c);
 
-// Exclusive prefix of n uint32 counts into n + 1 uint64 offsets (one workgroup).
+// Exclusive prefix of n uint32 counts into n + 1 uint64 offsets (one
+// workgroup for short inputs, three launches for long ones).
+uint64_t scan_blocks(uint64_t n);
 hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
                               uint64_t stride_out, uint64_t *out_strided, hipStream_t s);
 

@@ -116,15 +116,176 @@ k_peaks(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uint32_
     }
 }
 
+// Per-byte a >= b of four packed popcounts (each < 128): bit 7 of every
+// byte of the result.
+__device__ __forceinline__ uint32_t bytes_ge(uint32_t a, uint32_t b)
+{
+    return ((a | 0x80808080u) - b) & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t bytes_max(uint32_t a, uint32_t b)
+{
+    const uint32_t m = (bytes_ge(a, b) >> 7) * 0xFFu;
+    return (a & m) | (b & ~m);
+}
+
+__device__ __forceinline__ uint32_t popc4(uint32_t a, uint32_t b)
+{
+    // popcounts of the four uint16 halves of (a, b), one per byte
+    return uint32_t(__popc(a & 0xFFFFu)) | (uint32_t(__popc(a >> 16)) << 8) |
+           (uint32_t(__popc(b & 0xFFFFu)) << 16) | (uint32_t(__popc(b >> 16)) << 24);
+}
+
+// Vector form of k_peaks for n_phi >= 8 and a 16-byte aligned accumulator.
+// Staging reads 8 cells per 16-byte load; each thread tests 4 consecutive
+// cells at once on packed popcount bytes (neighbour maxima with per-byte
+// compares); with WRITE, a chunk's peaks are compacted into LDS in cell
+// order and stored with consecutive 8-byte writes.
+template <bool WRITE>
+__global__ void __launch_bounds__(256)
+k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uint32_t nphi,
+            uint32_t log2phi, uint32_t rp, uint32_t n_kt, uint32_t thr, uint32_t *__restrict__ tile_counts,
+            const uint64_t *__restrict__ tile_off, hough_peak *__restrict__ peaks, uint64_t capacity)
+{
+    HOUGH_DYNAMIC_LDS(uint4, lds4);
+    __shared__ uint32_t wave_cnt[4];
+    const uint32_t t = threadIdx.x, nt = blockDim.x;    // nt == 256
+    const uint32_t lane = t & 63, wave = t >> 6, nwaves = nt >> 6;
+    const uint32_t item = blockIdx.x;
+    const uint32_t per_event = n_d0 * n_kt;
+    const uint32_t e = item / per_event;
+    const uint32_t d = (item % per_event) / n_kt;
+    const uint32_t k0 = (item % n_kt) * rp;
+    const uint32_t nr = min(rp, n_qpt - k0);
+    const uint32_t planes = n_d0 > 1 ? 3 : 1;
+    const uint32_t prow = nr + 2;
+    const uint64_t cells = uint64_t(n_d0) * n_qpt * nphi;
+    const uint16_t *ev = acc + uint64_t(e) * cells;
+    // LDS: popcount bytes [planes][prow][nphi], then (WRITE) the raw centre
+    // rows [nr][nphi] uint16 and the chunk's records [nt * 4] uint2
+    uint8_t *pc = reinterpret_cast<uint8_t *>(lds4);
+    const size_t pc_bytes = (size_t(planes) * prow * nphi + 15) & ~size_t(15);
+    uint16_t *raw = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lds4) + pc_bytes);
+    uint2 *rec = reinterpret_cast<uint2 *>(reinterpret_cast<char *>(raw) + size_t(nr) * nphi * 2);
+
+    const uint32_t vpr = nphi >> 3;                     // 8-cell vectors per row
+    const uint32_t lv = log2phi - 3;
+    const uint32_t nvec = planes * prow * vpr;
+    const uint32_t cp = planes == 3 ? 1 : 0;
+    for (uint32_t i = t; i < nvec; i += nt) {
+        const uint32_t ri = i >> lv, col = i & (vpr - 1);
+        const uint32_t pl = planes == 1 ? 0 : (ri >= 2 * prow ? 2 : ri >= prow ? 1 : 0);
+        const uint32_t rr = ri - pl * prow;
+        const int dd = planes == 3 ? int(d) + int(pl) - 1 : int(d);
+        const int kk = int(k0) + int(rr) - 1;
+        uint2 packed = make_uint2(0u, 0u);
+        if (dd >= 0 && dd < int(n_d0) && kk >= 0 && kk < int(n_qpt)) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(ev + (uint64_t(dd) * n_qpt + kk) * nphi + col * 8);
+            packed = make_uint2(popc4(v.x, v.y), popc4(v.z, v.w));
+            if (WRITE && pl == cp && rr >= 1 && rr <= nr)
+                *reinterpret_cast<uint4 *>(raw + (rr - 1) * nphi + col * 8) = v;
+        }
+        *reinterpret_cast<uint2 *>(pc + size_t(ri) * nphi + col * 8) = packed;
+    }
+    __syncthreads();
+
+    const uint32_t tb = min(thr, 17u) * 0x01010101u;    // popcounts are <= 16
+    const uint32_t nquad = (nr * nphi) >> 2;
+    uint32_t count = 0;
+    uint64_t running = WRITE ? tile_off[item] : 0;
+    for (uint32_t base = 0; base < nquad; base += nt) {
+        const uint32_t q = base + t;
+        uint32_t bits = 0;                              // peak flags of 4 cells
+        if (q < nquad) {
+            const uint32_t rr = (q << 2) >> log2phi;
+            const uint32_t p0 = (q << 2) & (nphi - 1);
+            const uint32_t pm = (p0 - 4) & (nphi - 1), pn = (p0 + 4) & (nphi - 1);
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(pc + (cp * prow + rr + 1) * nphi + p0);
+            uint32_t m = 0;
+            for (uint32_t pl = 0; pl < planes; ++pl) {
+#pragma unroll
+                for (uint32_t dr = 0; dr < 3; ++dr) {
+                    const uint8_t *row = pc + (pl * prow + rr + dr) * nphi;
+                    const uint32_t w = *reinterpret_cast<const uint32_t *>(row + p0);
+                    const uint32_t wl = *reinterpret_cast<const uint32_t *>(row + pm);
+                    const uint32_t wr = *reinterpret_cast<const uint32_t *>(row + pn);
+                    m = bytes_max(m, bytes_max((w << 8) | (wl >> 24), (w >> 8) | (wr << 24)));
+                    if (!(pl == cp && dr == 1)) m = bytes_max(m, w);
+                }
+            }
+            const uint32_t f = bytes_ge(v, m) & bytes_ge(v, tb);
+            bits = ((f >> 7) & 1u) | ((f >> 14) & 2u) | ((f >> 21) & 4u) | ((f >> 28) & 8u);
+        }
+        const uint32_t c = __popc(bits);
+        if (!WRITE) {
+            count += c;
+            continue;
+        }
+        const uint64_t b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
+        const uint64_t lt = (1ull << lane) - 1ull;
+        const uint32_t before = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
+        if (lane == 0) wave_cnt[wave] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+        __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (uint32_t w = 0; w < nwaves; ++w) {
+            const uint32_t x = wave_cnt[w];
+            woff += w < wave ? x : 0;
+            total += x;
+        }
+        if (bits) {
+            const uint32_t rr = (q << 2) >> log2phi;
+            const uint32_t p0 = (q << 2) & (nphi - 1);
+            const uint32_t cell0 = uint32_t((uint64_t(d) * n_qpt + k0 + rr) * nphi + p0);
+            uint32_t o = woff + before;
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                if ((bits >> j) & 1u) {
+                    const uint32_t mk = raw[rr * nphi + p0 + j];
+                    rec[o++] = make_uint2(cell0 + j, mk | (uint32_t(__popc(mk)) << 16));
+                }
+            }
+        }
+        __syncthreads();
+        uint2 *out = reinterpret_cast<uint2 *>(peaks);
+        for (uint32_t i = t; i < total; i += nt) {
+            const uint64_t pos = running + i;
+            if (pos < capacity) out[pos] = rec[i];
+        }
+        running += total;
+        __syncthreads();
+    }
+    if (!WRITE) {
+        for (uint32_t off = 32; off > 0; off >>= 1) count += __shfl_down(count, off, 64);
+        if (lane == 0) wave_cnt[wave] = count;
+        __syncthreads();
+        if (t == 0) {
+            uint32_t s = 0;
+            for (uint32_t w = 0; w < nwaves; ++w) s += wave_cnt[w];
+            tile_counts[item] = s;
+        }
+    }
+}
+
 namespace {
+
+constexpr uint32_t kPeakThreads = 256;
+
+// LDS of one peak tile of rp rows: popcount bytes of the staged rows; the
+// vector kernel adds the raw centre rows and a chunk of records.
+size_t peaks_lds_bytes(const hough_ctx *c, uint32_t rp, bool vec)
+{
+    const uint32_t planes = c->spec.n_d0 > 1 ? 3 : 1;
+    const size_t pc = size_t(planes) * (rp + 2) * c->spec.n_phi;
+    if (!vec) return pc;
+    return ((pc + 15) & ~size_t(15)) + size_t(rp) * c->spec.n_phi * 2 + size_t(kPeakThreads) * 4 * 8;
+}
 
 // Rows per peak tile: the tuned or default value, reduced until the staged
 // popcount bytes fit in the LDS budget; 0 if a single row does not fit.
-uint32_t fit_rows(const hough_ctx *c)
+uint32_t fit_rows(const hough_ctx *c, bool vec)
 {
-    const uint32_t planes = c->spec.n_d0 > 1 ? 3 : 1;
     uint32_t rp = std::min(peak_rows(c), c->spec.n_qpt);
-    while (rp > 0 && size_t(planes) * (rp + 2) * c->spec.n_phi > c->max_lds) --rp;
+    while (rp > 0 && peaks_lds_bytes(c, rp, vec) > c->max_lds) --rp;
     return rp;
 }
 
@@ -134,29 +295,40 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
                         uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s)
 {
     hipError_t err;
-    const uint32_t rp = fit_rows(c);
+    const bool vec = c->spec.n_phi >= 8 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0 &&
+                     fit_rows(c, true) > 0;
+    const uint32_t rp = fit_rows(c, vec);
     if (rp == 0) return hipErrorInvalidConfiguration;
     const uint32_t n_kt = (c->spec.n_qpt + rp - 1) / rp;
     const uint64_t n_items = uint64_t(n_events) * c->spec.n_d0 * n_kt;
     if (n_events == 0) {
         return launch_scan_counts(c, c->d_tile_counts, 0, c->d_tile_off, 1, event_peak_offsets, s);
     }
-    const uint32_t planes = c->spec.n_d0 > 1 ? 3 : 1;
-    const size_t lds = size_t(planes) * (rp + 2) * c->spec.n_phi;
+    const size_t lds = peaks_lds_bytes(c, rp, vec);
     KernelTimer t;
     prof_begin(c, "peaks_count", s, &t);
-    hipLaunchKernelGGL(k_peaks<false>, dim3(uint32_t(n_items)), dim3(256), lds, s, acc, c->spec.n_d0,
-                       c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
-                       c->d_tile_counts, c->d_tile_off, peaks, capacity);
+    if (vec)
+        hipLaunchKernelGGL(k_peaks_vec<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads), peaks_lds_bytes(c, rp, false),
+                           s, acc, c->spec.n_d0, c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt,
+                           c->spec.threshold, c->d_tile_counts, c->d_tile_off, peaks, capacity);
+    else
+        hipLaunchKernelGGL(k_peaks<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
+                           c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
+                           c->d_tile_counts, c->d_tile_off, peaks, capacity);
     prof_end(c, s, &t);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = launch_scan_counts(c, c->d_tile_counts, n_items, c->d_tile_off,
                                   uint64_t(c->spec.n_d0) * n_kt, event_peak_offsets, s)) != hipSuccess)
         return err;
     prof_begin(c, "peaks_write", s, &t);
-    hipLaunchKernelGGL(k_peaks<true>, dim3(uint32_t(n_items)), dim3(256), lds, s, acc, c->spec.n_d0,
-                       c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
-                       c->d_tile_counts, c->d_tile_off, peaks, capacity);
+    if (vec)
+        hipLaunchKernelGGL(k_peaks_vec<true>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
+                           c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
+                           c->d_tile_counts, c->d_tile_off, peaks, capacity);
+    else
+        hipLaunchKernelGGL(k_peaks<true>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
+                           c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
+                           c->d_tile_counts, c->d_tile_off, peaks, capacity);
     prof_end(c, s, &t);
     return hipGetLastError();
 }

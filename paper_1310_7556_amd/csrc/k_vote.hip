@@ -134,6 +134,8 @@ uint32_t vote_rows(const hough_ctx *c)
 hipError_t launch_vote(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s)
 {
     if (h->n_events == 0) return hipSuccess;
+    if ((c->tun.vote_algo == 0 || c->tun.vote_algo == 4) && direct_vote_usable(c))
+        return launch_vote_direct(c, h, acc, s);
     if ((c->tun.vote_algo == 0 || c->tun.vote_algo == 3) && gap_vote_usable(c)) return launch_vote_gaps(c, h, acc, s);
     hipError_t err;
     const uint32_t R = vote_rows(c);

@@ -154,7 +154,8 @@ def ragged_batch():
 
 @pytest.mark.parametrize("tuning", [None, dict(vote_rows=1), dict(vote_rows=4, vote_threads=64),
                                     dict(vote_algo=1), dict(vote_algo=1, vote_rows=4, vote_threads=64),
-                                    dict(vote_algo=3, vote_rows=64, vote_threads=1024),
+                                    dict(vote_algo=3, vote_rows=64, vote_threads=1024), dict(vote_algo=3),
+                                    dict(vote_algo=4, vote_rows=64), dict(vote_algo=4, vote_rows=1, vote_threads=64),
                                     dict(vote_algo=2), dict(peak_rows=1), dict(peak_rows=7),
                                     dict(rz_slow_path=1), dict(vote_threads=1024, vote_wgs_per_cu=1)])
 def test_ragged_batch_with_empty_events(H, tuning):
@@ -200,20 +201,51 @@ def gap_layout_batch(n_phi):
     add([(4, [k * W for k in range(n_phi)]), (5, [k * (W + 1) for k in range(n_phi - 1)]),
          (6, [k * W + W - 1 for k in range(n_phi)] * 2)])
     add([(l, rng.integers(0, 1 << 32, 3 * n_phi)) for l in range(10)])
+    add([(l, rng.integers(0, 1 << 32, n_phi // 2)) for l in range(10)])
     return synth.concat_events(evs)
 
 
 @pytest.mark.parametrize("kw", [dict(n_phi=64, n_qpt=16), dict(n_phi=1024, n_qpt=8),
                                 dict(n_phi=64, n_qpt=8, n_d0=8, d0_lo_mm=-120.0, d0_hi_mm=120.0, n_z0=0)])
-def test_gap_vote_layer_layouts(H, kw):
+def test_vote_forms_on_layer_layouts(H, kw):
     spec = small_spec(**kw)
     batch = gap_layout_batch(spec["n_phi"])
     tab = oracle.Tables(spec)
-    gap = run_gpu(H, spec, batch, rz=False)
-    per_hit = run_gpu(H, spec, batch, tuning=dict(vote_algo=1), rz=False)
-    np.testing.assert_array_equal(H.acc_numpy(gap["acc"]), H.acc_numpy(per_hit["acc"]))
+    res = run_gpu(H, spec, batch, rz=False)
+    per_hit = H.acc_numpy(run_gpu(H, spec, batch, tuning=dict(vote_algo=1), rz=False)["acc"])
+    gaps = H.acc_numpy(run_gpu(H, spec, batch, tuning=dict(vote_algo=3), rz=False)["acc"])
+    np.testing.assert_array_equal(H.acc_numpy(res["acc"]), per_hit)
+    np.testing.assert_array_equal(gaps, per_hit)
     for e in range(batch.n_events):
-        check_event(H, tab, gap, batch, e)
+        check_event(H, tab, res, batch, e)
+
+
+def test_unaligned_hit_arrays_and_accumulator(H):
+    """Hit arrays that start one element past an aligned address and an
+    accumulator that is 4- but not 16-byte aligned take the scalar load and
+    store paths of the vote; results are unchanged."""
+    import torch
+    spec = small_spec(n_phi=256, n_qpt=16)
+    batch = ragged_batch()
+    ctx = H.HoughContext(spec, max_events=batch.n_events, max_hits=batch.n_hits)
+    n = batch.n_hits
+    lay = torch.zeros(n + 1, dtype=torch.uint8, device="cuda")[1:]
+    lay.copy_(torch.from_numpy(batch.layer.astype(np.uint8)))
+    phi = torch.zeros(n + 1, dtype=torch.int32, device="cuda")[1:]
+    phi.copy_(torch.from_numpy(batch.phi.astype(np.uint32).view(np.int32)))
+    hits = H.DeviceHits(lay, phi, None, batch.offsets)
+    assert hits.layer.data_ptr() % 4 and hits.phi.data_ptr() % 16
+    base = ctx.new_acc(batch.n_events + 1).view(-1)
+    acc = base[2:2 + batch.n_events * ctx.cells].view(batch.n_events, -1)
+    assert acc.data_ptr() % 16
+    ctx.vote(hits, acc)
+    torch.cuda.synchronize()
+    tab = oracle.Tables(spec)
+    got = H.acc_numpy(acc)
+    for e in range(batch.n_events):
+        ev = batch.event(e)
+        A = oracle.vote_mask(tab, ev.layer, ev.phi)
+        np.testing.assert_array_equal(got[e].reshape(A.shape), A, err_msg=f"event {e}")
 
 
 def test_displaced_small_grid_unreachable_rows(H):
@@ -359,6 +391,6 @@ def test_limits_and_bad_arguments_raise(H):
     with pytest.raises(H.HoughError):
         ctx.set_tuning(vote_rows=3)
     with pytest.raises(H.HoughError):
-        ctx.set_tuning(vote_algo=4)
+        ctx.set_tuning(vote_algo=5)
     with pytest.raises(H.HoughError):
         H.HoughContext(dict(spec, n_phi=48))
