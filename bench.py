@@ -102,14 +102,14 @@ def bench_single(H, torch, steps, warmup):
         achieved = rz_votes * RZ_OPS_PER_VOTE / t / 1e12
         out["roofline"] = dict(kernel="rz_vote", bound="alu", achieved=round(achieved, 4),
                                peak=round(ALU_PEAK_TOPS, 2), unit="TOP/s",
-                               frac=round(achieved / ALU_PEAK_TOPS, 5), traffic=None,
+                               frac=round(achieved / ALU_PEAK_TOPS, 5), traffic=recorded_traffic("rz_vote"),
                                work_per_launch=f"{rz_votes} member x cot votes x {RZ_OPS_PER_VOTE} int ops")
     else:
         t = kernel_avg_ms(times, dom) * 1e-3
         byts = VOTE_KERNEL_BYTES.get(dom, lambda n_hits, cells: 2 * cells)(ev.n_hits, ctx.cells)
         gbs = byts / t / 1e9
         out["roofline"] = dict(kernel=dom, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
-                               unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None)
+                               unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=recorded_traffic(dom))
     out["rz_votes_per_s"] = rz_votes / (ms * 1e-3)
     return out, (spec, ev)
 
@@ -200,11 +200,111 @@ def bench_batched(H, torch, reps=5):
         speedup_vs_plain=round(t_plain / t_graph, 3),
         stage_ms={k: round(v[1] / v[0], 4) for k, v in times.items() if v[0]},
         roofline=dict(kernel=vk, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
-                      unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None,
+                      unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=recorded_traffic(vk),
                       bytes_per_launch=vote_bytes),
         vote_stage=dict(kernels_ms=round(t_stage * 1e3, 4), bytes=stage_bytes,
                         achieved_gbs=round(stage_bytes / t_stage / 1e9, 2),
                         frac=round(stage_bytes / t_stage / 1e9 / HBM_PEAK_GBS, 5)))
+
+
+# --- HBM traffic of the dominant kernels ---------------------------------
+# `--traffic-probe` runs, once each: a plain device-to-device copy of
+# COPY_BYTES (the calibration kernel), one c2 step and one c4 vote + peaks.
+# It is meant to run under `rocprofv3 --pmc FETCH_SIZE` and, separately,
+# `--pmc WRITE_SIZE`; `--summarize-traffic FETCH_CSV WRITE_CSV` turns the two
+# counter files into TRAFFIC_FILE.  A kernel's entry holds the SHA-256 of its
+# source file, and the bench reports `traffic` only while it still matches.
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+TRAFFIC_KERNELS = {
+    # bench name: (rocprofv3 kernel-name prefix, source file, workload)
+    "rz_vote": ("hough::k_rz_vote", "paper_1310_7556_amd/csrc/k_rz.hip", "c2_single_1ktrk_rz"),
+    "vote_direct": ("hough::k_vote_direct", "paper_1310_7556_amd/csrc/k_vote_direct.hip", "c4_batch_4096"),
+}
+
+
+def source_sha(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_probe(H, torch):
+    import synth
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    log("probe: copy")
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("probe: c2 step")
+    name = "c2_single_1ktrk_rz"
+    spec, ev = synth.grid_spec(name), synth.gen_config(name)
+    ctx = H.HoughContext(spec, max_events=1, max_hits=ev.n_hits)
+    hits = H.DeviceHits.from_batch(ev)
+    acc = ctx.vote(hits)
+    pk, poff = ctx.peaks(acc, 1, capacity=ctx.cells)
+    ctx.rz_refine(hits, pk, poff, capacity=ctx.cells)
+    torch.cuda.synchronize()
+    del ctx, hits, acc, pk, poff
+    log("probe: c4 vote + peaks")
+    name = "c4_batch_4096"
+    spec, batch = synth.grid_spec(name), synth.gen_config(name)
+    E = batch.n_events
+    ctx = H.HoughContext(spec, max_events=E, max_hits=batch.n_hits)
+    hits = H.DeviceHits.from_batch(batch)
+    acc = ctx.vote(hits)
+    ctx.peaks(acc, E, capacity=E * ctx.cells)
+    torch.cuda.synchronize()
+    log("probe: done")
+
+
+def summarize_traffic(fetch_csv, write_csv):
+    import csv
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"][5:] if r["Kernel_Name"].startswith("void ") else r["Kernel_Name"]
+            per.setdefault((counter, name), []).append(float(r["Counter_Value"]) * 1024.0)
+
+    def largest(counter, prefix):
+        # the probe's largest dispatch of the kernel is the named workload's
+        vals = [v for (c, k), vs in per.items() if c == counter and k.startswith(prefix) for v in vs]
+        return (max(vals), len(vals)) if vals else (None, 0)
+
+    # the copy moves COPY_BYTES each way; blit launches of other copies are far smaller
+    big_f = max(v for (c, k), vs in per.items() if c == "FETCH_SIZE" and k.startswith("__amd_rocclr_copyBuffer")
+                for v in vs)
+    big_w = max(v for (c, k), vs in per.items() if c == "WRITE_SIZE" and k.startswith("__amd_rocclr_copyBuffer")
+                for v in vs)
+    ff, fw = COPY_BYTES / big_f, COPY_BYTES / big_w
+    out = dict(calibration=dict(copy_bytes=COPY_BYTES, fetch_counter_bytes=big_f, write_counter_bytes=big_w,
+                                fetch_factor=ff, write_factor=fw),
+               kernels={})
+    for name, (prefix, src, workload) in TRAFFIC_KERNELS.items():
+        f, nf = largest("FETCH_SIZE", prefix)
+        w, nw = largest("WRITE_SIZE", prefix)
+        if f is None or w is None:
+            continue
+        out["kernels"][name] = dict(source=src, sha256=source_sha(src), workload=workload, dispatches=[nf, nw],
+                                    fetch_bytes=f * ff, write_bytes=w * fw, bytes_per_launch=f * ff + w * fw)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def recorded_traffic(name):
+    """HBM bytes per launch of kernel `name` from TRAFFIC_FILE, or None when
+    absent or when its source has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            k = json.load(fh)["kernels"][name]
+    except (OSError, KeyError, ValueError):
+        return None
+    return round(k["bytes_per_launch"]) if source_sha(k["source"]) == k["sha256"] else None
 
 
 def cpu_baseline(spec, ev):
@@ -227,7 +327,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the copy/c2/c4 kernels once each (for rocprofv3 --pmc runs) and exit")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic file from two rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: events are independent, so more GPUs would "
               "shard whole events with no exchange; run with --gpus 1.", file=sys.stderr)
@@ -236,6 +343,9 @@ def main():
     from paper_1310_7556_amd import hough as H
     H.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.traffic_probe:
+        traffic_probe(H, torch)
+        return
 
     log("c2 single-event steps ...")
     single, (spec, ev) = bench_single(H, torch, args.steps, args.warmup)
