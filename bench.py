@@ -55,12 +55,24 @@ def kernel_avg_ms(times, name):
     return ms / n if n else float("nan")
 
 
+def apply_cached_tuning(ctx, torch, spec, n_events, n_hits):
+    """The autotuner's cached launch parameters for this workload, applied
+    to ctx; returns them, or "default" when the cache has no entry."""
+    from paper_1310_7556_amd import tune
+    t = tune.lookup(tune.workload_key(spec, n_events, n_hits, tune.device_name(torch)))
+    if not t:
+        return "default"
+    ctx.set_tuning(**t)
+    return t
+
+
 def bench_single(H, torch, steps, warmup):
     import synth
     name = "c2_single_1ktrk_rz"
     spec = synth.grid_spec(name)
     ev = synth.gen_config(name)
     ctx = H.HoughContext(spec, max_events=1, max_hits=ev.n_hits)
+    tuning = apply_cached_tuning(ctx, torch, spec, 1, ev.n_hits)
     hits = H.DeviceHits.from_batch(ev)
     acc = ctx.new_acc(1)
     cap = ctx.cells
@@ -95,7 +107,7 @@ def bench_single(H, torch, steps, warmup):
     stage = {k: round(v[1] / v[0], 5) for k, v in times.items() if v[0]}
     dom = max(times, key=lambda k: times[k][1])
     out = dict(ms_per_step=ms, rphi_votes=rphi_votes, rz_votes=rz_votes, n_peaks=n_peaks,
-               n_hits=ev.n_hits, stage_ms=stage, dominant=dom, stream=int(stream.cuda_stream))
+               n_hits=ev.n_hits, stage_ms=stage, dominant=dom, stream=int(stream.cuda_stream), tuning=tuning)
     # roofline of the dominant kernel
     if dom == "rz_vote":
         t = kernel_avg_ms(times, "rz_vote") * 1e-3
@@ -123,6 +135,7 @@ def bench_batched(H, torch, reps=5):
     log(f"c4: generated {batch.n_events} events, {batch.n_hits} hits in {time.perf_counter() - t0:.1f}s")
     E = batch.n_events
     ctx = H.HoughContext(spec, max_events=E, max_hits=batch.n_hits)
+    tuning = apply_cached_tuning(ctx, torch, spec, E, batch.n_hits)
     hits = H.DeviceHits.from_batch(batch)
     acc = ctx.new_acc(E)
     cap = E * ctx.cells
@@ -194,7 +207,7 @@ def bench_batched(H, torch, reps=5):
     votes = batch.n_hits * spec["n_qpt"]
     g.close()
     return dict(
-        workload=name, n_events=E, n_hits=batch.n_hits, votes=votes, peaks=total_peaks,
+        workload=name, n_events=E, n_hits=batch.n_hits, votes=votes, peaks=total_peaks, tuning=tuning,
         graph_ms=round(t_graph * 1e3, 3), events_per_s=E / t_graph, votes_per_s=votes / t_graph,
         plain_ms=round(t_plain * 1e3, 3), plain_events_per_s=E / t_plain,
         speedup_vs_plain=round(t_plain / t_graph, 3),
@@ -361,6 +374,7 @@ def main():
         rz_votes_per_s=single["rz_votes_per_s"],
         peaks_per_event=single["n_peaks"],
         stage_ms=single["stage_ms"],
+        tuning=single["tuning"],
         roofline=single["roofline"],
     )
     if not args.no_batched:
