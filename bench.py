@@ -30,6 +30,9 @@ METRIC = "Hough votes/s and events/s (1k-track event); batched vs plain; serving
 HBM_PEAK_GBS = 8000.0
 # int32 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS atomics: 32 banks per CU, one read-modify-write per bank every two
+# cycles (an estimate from the LDS width, not a published figure)
+LDS_ATOMIC_PEAK = 256 * 32 / 2 * 2.4e9
 # integer operations per rz (member, cot bin) vote: z - Z, - z0_lo, range
 # test, * n_z0, / span, histogram increment, running-maximum compare
 RZ_OPS_PER_VOTE = 7
@@ -123,6 +126,10 @@ def bench_single(H, torch, steps, warmup):
         out["roofline"] = dict(kernel=dom, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
                                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=recorded_traffic(dom))
     out["rz_votes_per_s"] = rz_votes / (ms * 1e-3)
+    # k_rz_vote_fast issues one LDS atomic add per (member, cot bin) vote
+    t_rz = kernel_avg_ms(times, "rz_vote") * 1e-3
+    out["atomics"] = dict(kernel="rz_vote", space="lds", per_launch=rz_votes, per_s=rz_votes / t_rz,
+                          peak_estimate=LDS_ATOMIC_PEAK, frac=round(rz_votes / t_rz / LDS_ATOMIC_PEAK, 5))
     return out, (spec, ev)
 
 
@@ -170,6 +177,27 @@ def bench_batched(H, torch, reps=5):
                                                      "vote_lds", "bucket_layers")
                   if k in times) * 1e-3
 
+    # the per-hit LDS-atomic form of the vote (the paper's recipe), timed once
+    # for its atomic throughput: one LDS atomic OR per (hit, row)
+    with torch.cuda.stream(stream):
+        ctx.set_tuning(vote_algo=1)
+        ctx.vote(hits, acc, stream=stream)
+        stream.synchronize()
+        ctx.kernel_times_reset()
+        ctx.set_profiling(True)
+        ctx.vote(hits, acc, stream=stream)
+        stream.synchronize()
+        ctx.set_profiling(False)
+        t_atomic = kernel_avg_ms(ctx.kernel_times(), "vote_lds") * 1e-3
+        if isinstance(tuning, dict):
+            ctx.set_tuning(**tuning)
+        else:
+            ctx.set_tuning()
+    n_atomics = batch.n_hits * spec["n_qpt"] * spec["n_d0"]
+    atomics = dict(kernel="vote_lds", space="lds", per_launch=n_atomics, per_s=n_atomics / t_atomic,
+                   peak_estimate=LDS_ATOMIC_PEAK, frac=round(n_atomics / t_atomic / LDS_ATOMIC_PEAK, 5),
+                   ms=round(t_atomic * 1e3, 3))
+
     # plain path: one event per launch, same kernels, same GPU
     import ctypes as C
     lib = ctx.lib
@@ -208,6 +236,7 @@ def bench_batched(H, torch, reps=5):
     g.close()
     return dict(
         workload=name, n_events=E, n_hits=batch.n_hits, votes=votes, peaks=total_peaks, tuning=tuning,
+        per_hit_atomic_vote=atomics,
         graph_ms=round(t_graph * 1e3, 3), events_per_s=E / t_graph, votes_per_s=votes / t_graph,
         plain_ms=round(t_plain * 1e3, 3), plain_events_per_s=E / t_plain,
         speedup_vs_plain=round(t_plain / t_graph, 3),
@@ -372,6 +401,10 @@ def main():
                     n_hits=single["n_hits"], grid=[1024, 1024], rz=[256, 256]),
         events_per_s=1e3 / single["ms_per_step"],
         rz_votes_per_s=single["rz_votes_per_s"],
+        atomics=single["atomics"],
+        paper_context=("the paper prints no absolute timings; its Figure 2 (2048x2048 grid, toy Monte "
+                       "Carlo) has a Tesla K20c about as fast as 2x Xeon E5-2697v2, Xeon Phi 7120P 3x and "
+                       "i7-3770 5x slower at 5000 tracks"),
         peaks_per_event=single["n_peaks"],
         stage_ms=single["stage_ms"],
         tuning=single["tuning"],

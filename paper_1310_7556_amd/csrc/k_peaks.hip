@@ -116,31 +116,38 @@ k_peaks(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uint32_
     }
 }
 
-// Per-byte a >= b of four packed popcounts (each < 128): bit 7 of every
-// byte of the result.
-__device__ __forceinline__ uint32_t bytes_ge(uint32_t a, uint32_t b)
+// Two 16-bit lanes per 32-bit word: max of each half.  On the GPU one
+// packed-integer instruction (v_pk_max_u16); the expression in the other
+// branch is the same arithmetic for host compilation.
+__device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b)
 {
-    return ((a | 0x80808080u) - b) & 0x80808080u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+#else
+    return max(a & 0xFFFFu, b & 0xFFFFu) | (max(a >> 16, b >> 16) << 16);
+#endif
 }
 
-__device__ __forceinline__ uint32_t bytes_max(uint32_t a, uint32_t b)
+// (hi:lo) >> 16: the pair of cells one position to the right of `lo`
+__device__ __forceinline__ uint32_t shift_pair(uint32_t hi, uint32_t lo)
 {
-    const uint32_t m = (bytes_ge(a, b) >> 7) * 0xFFu;
-    return (a & m) | (b & ~m);
+    return (lo >> 16) | (hi << 16);
 }
 
-__device__ __forceinline__ uint32_t popc4(uint32_t a, uint32_t b)
+__device__ __forceinline__ uint32_t popc2(uint32_t a)
 {
-    // popcounts of the four uint16 halves of (a, b), one per byte
-    return uint32_t(__popc(a & 0xFFFFu)) | (uint32_t(__popc(a >> 16)) << 8) |
-           (uint32_t(__popc(b & 0xFFFFu)) << 16) | (uint32_t(__popc(b >> 16)) << 24);
+    // popcounts of the two uint16 halves of a, one per half
+    return uint32_t(__popc(a & 0xFFFFu)) | (uint32_t(__popc(a >> 16)) << 16);
 }
 
 // Vector form of k_peaks for n_phi >= 8 and a 16-byte aligned accumulator.
-// Staging reads 8 cells per 16-byte load; each thread tests 4 consecutive
-// cells at once on packed popcount bytes (neighbour maxima with per-byte
-// compares); with WRITE, a chunk's peaks are compacted into LDS in cell
-// order and stored with consecutive 8-byte writes.
+// Staging reads 8 cells per 16-byte load and keeps their popcounts as
+// 16-bit pairs; each thread tests 4 consecutive cells, two per word, with
+// packed 16-bit maxima of the shifted neighbour pairs; with WRITE, a
+// chunk's peaks are compacted into LDS in cell order and stored with
+// consecutive 8-byte writes.
 template <bool WRITE>
 __global__ void __launch_bounds__(256)
 k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uint32_t nphi,
@@ -161,10 +168,10 @@ k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uin
     const uint32_t prow = nr + 2;
     const uint64_t cells = uint64_t(n_d0) * n_qpt * nphi;
     const uint16_t *ev = acc + uint64_t(e) * cells;
-    // LDS: popcount bytes [planes][prow][nphi], then (WRITE) the raw centre
-    // rows [nr][nphi] uint16 and the chunk's records [nt * 4] uint2
-    uint8_t *pc = reinterpret_cast<uint8_t *>(lds4);
-    const size_t pc_bytes = (size_t(planes) * prow * nphi + 15) & ~size_t(15);
+    // LDS: popcounts [planes][prow][nphi] as uint16, then (WRITE) the raw
+    // centre rows [nr][nphi] uint16 and the chunk's records [nt * 4] uint2
+    uint16_t *pc = reinterpret_cast<uint16_t *>(lds4);
+    const size_t pc_bytes = (size_t(planes) * prow * nphi * 2 + 15) & ~size_t(15);
     uint16_t *raw = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lds4) + pc_bytes);
     uint2 *rec = reinterpret_cast<uint2 *>(reinterpret_cast<char *>(raw) + size_t(nr) * nphi * 2);
 
@@ -178,18 +185,18 @@ k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uin
         const uint32_t rr = ri - pl * prow;
         const int dd = planes == 3 ? int(d) + int(pl) - 1 : int(d);
         const int kk = int(k0) + int(rr) - 1;
-        uint2 packed = make_uint2(0u, 0u);
+        uint4 packed = make_uint4(0u, 0u, 0u, 0u);
         if (dd >= 0 && dd < int(n_d0) && kk >= 0 && kk < int(n_qpt)) {
             const uint4 v = *reinterpret_cast<const uint4 *>(ev + (uint64_t(dd) * n_qpt + kk) * nphi + col * 8);
-            packed = make_uint2(popc4(v.x, v.y), popc4(v.z, v.w));
+            packed = make_uint4(popc2(v.x), popc2(v.y), popc2(v.z), popc2(v.w));
             if (WRITE && pl == cp && rr >= 1 && rr <= nr)
                 *reinterpret_cast<uint4 *>(raw + (rr - 1) * nphi + col * 8) = v;
         }
-        *reinterpret_cast<uint2 *>(pc + size_t(ri) * nphi + col * 8) = packed;
+        *reinterpret_cast<uint4 *>(pc + size_t(ri) * nphi + col * 8) = packed;
     }
     __syncthreads();
 
-    const uint32_t tb = min(thr, 17u) * 0x01010101u;    // popcounts are <= 16
+    const uint32_t t2 = min(thr, 17u) * 0x00010001u;    // popcounts are <= 16
     const uint32_t nquad = (nr * nphi) >> 2;
     uint32_t count = 0;
     uint64_t running = WRITE ? tile_off[item] : 0;
@@ -199,22 +206,30 @@ k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uin
         if (q < nquad) {
             const uint32_t rr = (q << 2) >> log2phi;
             const uint32_t p0 = (q << 2) & (nphi - 1);
-            const uint32_t pm = (p0 - 4) & (nphi - 1), pn = (p0 + 4) & (nphi - 1);
-            const uint32_t v = *reinterpret_cast<const uint32_t *>(pc + (cp * prow + rr + 1) * nphi + p0);
-            uint32_t m = 0;
+            const uint32_t pm = (p0 - 2) & (nphi - 1), pn = (p0 + 4) & (nphi - 1);
+            const uint2 vv = *reinterpret_cast<const uint2 *>(pc + (cp * prow + rr + 1) * nphi + p0);
+            uint32_t m0 = t2, m1 = t2;                  // neighbour maxima, threshold folded in
             for (uint32_t pl = 0; pl < planes; ++pl) {
 #pragma unroll
                 for (uint32_t dr = 0; dr < 3; ++dr) {
-                    const uint8_t *row = pc + (pl * prow + rr + dr) * nphi;
-                    const uint32_t w = *reinterpret_cast<const uint32_t *>(row + p0);
-                    const uint32_t wl = *reinterpret_cast<const uint32_t *>(row + pm);
-                    const uint32_t wr = *reinterpret_cast<const uint32_t *>(row + pn);
-                    m = bytes_max(m, bytes_max((w << 8) | (wl >> 24), (w >> 8) | (wr << 24)));
-                    if (!(pl == cp && dr == 1)) m = bytes_max(m, w);
+                    const uint16_t *row = pc + (pl * prow + rr + dr) * nphi;
+                    const uint2 w = *reinterpret_cast<const uint2 *>(row + p0);       // cells p0..p0+3
+                    const uint32_t wl = *reinterpret_cast<const uint32_t *>(row + pm);  // p0-2, p0-1
+                    const uint32_t wr = *reinterpret_cast<const uint32_t *>(row + pn);  // p0+4, p0+5
+                    const uint32_t mid = shift_pair(w.y, w.x);                          // p0+1, p0+2
+                    m0 = pk_max_u16(m0, pk_max_u16(shift_pair(w.x, wl), mid));          // p0-1.. / p0+1..
+                    m1 = pk_max_u16(m1, pk_max_u16(mid, shift_pair(wr, w.y)));
+                    if (!(pl == cp && dr == 1)) {
+                        m0 = pk_max_u16(m0, w.x);
+                        m1 = pk_max_u16(m1, w.y);
+                    }
                 }
             }
-            const uint32_t f = bytes_ge(v, m) & bytes_ge(v, tb);
-            bits = ((f >> 7) & 1u) | ((f >> 14) & 2u) | ((f >> 21) & 4u) | ((f >> 28) & 8u);
+            // a cell is a peak iff its popcount is >= every neighbour and >= thr:
+            // max(m, v) == v in its half
+            const uint32_t x0 = pk_max_u16(m0, vv.x) ^ vv.x, x1 = pk_max_u16(m1, vv.y) ^ vv.y;
+            bits = ((x0 & 0xFFFFu) == 0 ? 1u : 0u) | ((x0 >> 16) == 0 ? 2u : 0u) |
+                   ((x1 & 0xFFFFu) == 0 ? 4u : 0u) | ((x1 >> 16) == 0 ? 8u : 0u);
         }
         const uint32_t c = __popc(bits);
         if (!WRITE) {
@@ -270,14 +285,17 @@ namespace {
 
 constexpr uint32_t kPeakThreads = 256;
 
-// LDS of one peak tile of rp rows: popcount bytes of the staged rows; the
-// vector kernel adds the raw centre rows and a chunk of records.
-size_t peaks_lds_bytes(const hough_ctx *c, uint32_t rp, bool vec)
+// LDS of one peak tile of rp rows: popcounts of the staged rows (bytes in
+// the scalar kernel, uint16 in the vector one, which with WRITE adds the raw
+// centre rows and a chunk of records).
+size_t peaks_lds_bytes(const hough_ctx *c, uint32_t rp, bool vec, bool write = true)
 {
     const uint32_t planes = c->spec.n_d0 > 1 ? 3 : 1;
     const size_t pc = size_t(planes) * (rp + 2) * c->spec.n_phi;
     if (!vec) return pc;
-    return ((pc + 15) & ~size_t(15)) + size_t(rp) * c->spec.n_phi * 2 + size_t(kPeakThreads) * 4 * 8;
+    const size_t pc16 = (2 * pc + 15) & ~size_t(15);
+    if (!write) return pc16;
+    return pc16 + size_t(rp) * c->spec.n_phi * 2 + size_t(kPeakThreads) * 4 * 8;
 }
 
 // Rows per peak tile: the tuned or default value, reduced until the staged
@@ -308,7 +326,8 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
     KernelTimer t;
     prof_begin(c, "peaks_count", s, &t);
     if (vec)
-        hipLaunchKernelGGL(k_peaks_vec<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads), peaks_lds_bytes(c, rp, false),
+        hipLaunchKernelGGL(k_peaks_vec<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads),
+                           peaks_lds_bytes(c, rp, true, false),
                            s, acc, c->spec.n_d0, c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt,
                            c->spec.threshold, c->d_tile_counts, c->d_tile_off, peaks, capacity);
     else
