@@ -52,6 +52,8 @@ def _load():
         lib.orc_vote_count.argtypes = [P, P, P, C.c_uint64, P, P, P]
         lib.orc_peaks.argtypes = [P, P, P, P, P, C.c_uint64]
         lib.orc_peaks.restype = C.c_uint64
+        lib.orc_peaks_count.argtypes = [P, P, P, P, C.c_uint64]
+        lib.orc_peaks_count.restype = C.c_uint64
         lib.orc_rz_candidates.argtypes = [P, C.c_uint64, P, P]
         lib.orc_rz_candidates.restype = C.c_uint64
         lib.orc_rz.argtypes = [P, P, P, P, C.c_uint64, P, P, P, C.c_uint64, P, P,
@@ -153,6 +155,21 @@ def peaks(tab, A):
     n = _load().orc_peaks(C.byref(tab.cs), _p(A), _p(cell), _p(mask), _p(pc), cap)
     out = np.zeros(n, PEAK_DTYPE)
     out["cell"], out["mask"], out["popcount"] = cell[:n], mask[:n], pc[:n]
+    return out
+
+
+COUNT_PEAK_DTYPE = np.dtype([("cell", np.uint32), ("count", np.uint32)])
+
+
+def peaks_count(tab, Cc):
+    """Local maxima of one event's counting accumulator, ascending by cell."""
+    Cc = np.ascontiguousarray(Cc, np.uint32).reshape(-1)
+    cap = Cc.size
+    cell = np.zeros(cap, np.uint32)
+    cnt = np.zeros(cap, np.uint32)
+    n = _load().orc_peaks_count(C.byref(tab.cs), _p(Cc), _p(cell), _p(cnt), cap)
+    out = np.zeros(n, COUNT_PEAK_DTYPE)
+    out["cell"], out["count"] = cell[:n], cnt[:n]
     return out
 
 

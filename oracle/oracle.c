@@ -221,6 +221,47 @@ uint64_t orc_peaks(const orc_spec *g, const uint16_t *A,
     return n;
 }
 
+/* Local maxima of the counting accumulator (the paper's A[B[i]] += 1 form,
+ * Section 7): the same rule as orc_peaks with the cell's vote count in place
+ * of its popcount -- count >= threshold and >= the count of every
+ * neighbour (3x3, 3x3x3 with a d0 axis; phi0 periodic).  Ascending cell
+ * order; returns the true number of peaks, records past cap dropped. */
+uint64_t orc_peaks_count(const orc_spec *g, const uint32_t *C, uint32_t *cell, uint32_t *count,
+                         uint64_t cap)
+{
+    uint64_t n = 0;
+    int nd = (int)g->n_d0, nk = (int)g->n_qpt, np = (int)g->n_phi;
+    for (int d = 0; d < nd; d++)
+        for (int k = 0; k < nk; k++)
+            for (int p = 0; p < np; p++) {
+                size_t c = ((size_t)d * nk + k) * np + p;
+                uint32_t v = C[c];
+                if (v < g->threshold) continue;
+                int is_max = 1;
+                for (int dd = -1; dd <= 1 && is_max; dd++) {
+                    if (nd == 1 && dd != 0) continue;
+                    int d2 = d + dd;
+                    if (d2 < 0 || d2 >= nd) continue;
+                    for (int dk = -1; dk <= 1 && is_max; dk++) {
+                        int k2 = k + dk;
+                        if (k2 < 0 || k2 >= nk) continue;
+                        for (int dp = -1; dp <= 1; dp++) {
+                            if (dd == 0 && dk == 0 && dp == 0) continue;
+                            int p2 = ((p + dp) % np + np) % np;
+                            if (C[((size_t)d2 * nk + k2) * np + p2] > v) { is_max = 0; break; }
+                        }
+                    }
+                }
+                if (!is_max) continue;
+                if (n < cap) {
+                    cell[n] = (uint32_t)c;
+                    count[n] = v;
+                }
+                n++;
+            }
+    return n;
+}
+
 /* ---- rz refinement (O5) ----------------------------------------------- */
 
 static int64_t floor_div64(int64_t a, int64_t b)

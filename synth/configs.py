@@ -14,10 +14,15 @@ B_TESLA = 3.8
 Z_ACCEPT_MM = 1200.0
 
 
+# The paper's own toy detector (Section 3): 10 evenly spaced layers out to
+# 1.1 m (read as r = 11 i cm), 0.4 mm hit resolution.
+PAPER_R_MM = tuple(110.0 * i for i in range(1, 11))
+
+
 def _spec(n_qpt, n_phi, threshold, n_d0=1, d0=(0.0, 0.0), rz=False,
-          rz_max_candidates=0):
+          rz_max_candidates=0, radii=DETECTOR_R_MM):
     s = dict(
-        n_layers=len(DETECTOR_R_MM), layer_r_mm=list(DETECTOR_R_MM),
+        n_layers=len(radii), layer_r_mm=list(radii),
         b_tesla=B_TESLA,
         n_qpt=n_qpt, qpt_lo=-1.0, qpt_hi=1.0,
         n_phi=n_phi,
@@ -56,6 +61,12 @@ CONFIGS = {
         index=4, n_events=None, tracks=("loguniform", 100, 10000),
         noise_per_track_hit=5, displaced_frac=0.0,
         spec=_spec(512, 512, 8, rz=True, rz_max_candidates=1024)),
+    # the paper's counting accumulator on its 2048 x 2048 grid and detector
+    # (time vs number of tracks is swept by passing n_tracks to gen_event)
+    "p6_paper_2048_count": dict(
+        index=5, n_events=1, tracks=("fixed", 1000), noise=0,
+        displaced_frac=0.0, sigma_rphi_mm=0.4,
+        spec=_spec(2048, 2048, 8, radii=PAPER_R_MM)),
 }
 
 

@@ -92,7 +92,7 @@ def _helix_hits(kappa, phi0, d0, cot, z0, radii, b_tesla):
 
 
 def track_hits(kappa, phi0, d0=0.0, cot=0.0, z0=0.0, radii=DETECTOR_R_MM,
-               b_tesla=B_TESLA, rng=None, drop_layers=()):
+               b_tesla=B_TESLA, rng=None, drop_layers=(), sigma_rphi_mm=SIGMA_RPHI_MM):
     """Hits of tracks with the given true parameters (noiseless unless rng).
 
     Scalars or arrays of equal length.  Returns (layer u8, phi u32, z i32).
@@ -104,7 +104,7 @@ def track_hits(kappa, phi0, d0=0.0, cot=0.0, z0=0.0, radii=DETECTOR_R_MM,
     phi, z, ok = _helix_hits(kappa, phi0, d0, cot, z0, radii, b_tesla)
     radii = np.asarray(radii, np.float64)
     if rng is not None:
-        phi = phi + rng.normal(0.0, 1.0, phi.shape) * (SIGMA_RPHI_MM / radii[None, :])
+        phi = phi + rng.normal(0.0, 1.0, phi.shape) * (sigma_rphi_mm / radii[None, :])
         z = z + rng.normal(0.0, SIGMA_Z_MM, z.shape)
     ok = ok & (np.abs(z) < Z_ACCEPT_MM)
     for l in drop_layers:
@@ -145,7 +145,8 @@ def gen_event(cfg, rng, n_tracks=None):
         n_disp = int(round(frac * n_tracks))
         lo, hi = cfg["d0_range_mm"]
         d0[:n_disp] = rng.uniform(lo, hi, n_disp)
-    layer, phi, z = track_hits(kappa, phi0, d0, cot, z0, radii, spec["b_tesla"], rng=rng)
+    layer, phi, z = track_hits(kappa, phi0, d0, cot, z0, radii, spec["b_tesla"], rng=rng,
+                               sigma_rphi_mm=cfg.get("sigma_rphi_mm", SIGMA_RPHI_MM))
     n_track_hits = len(layer)
     if "noise_per_track_hit" in cfg:
         n_noise = int(cfg["noise_per_track_hit"] * n_track_hits)

@@ -471,3 +471,66 @@ def test_spec_validation():
     assert not oracle.check_spec(bad)
     bad = tiny_spec(n_d0=4, d0=(-10, 10), rz=True)
     assert not oracle.check_spec(bad)
+
+
+# --------------------------------------------------------------------------
+# the counting form's local maxima (the paper's A[B[i]] += 1 accumulator)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_d0,lam", [(1, 1.0), (1, 4.0), (3, 2.5)])
+def test_count_peaks_match_maximum_filter(n_d0, lam):
+    spec = tiny_spec(n_qpt=24, n_phi=32, n_d0=n_d0, d0=(-50.0, 50.0), threshold=3)
+    tab = oracle.Tables(spec)
+    rng = np.random.default_rng(int(lam * 10) + n_d0)
+    Cc = rng.poisson(lam, (n_d0, 24, 32)).astype(np.uint32)
+    Cc[0, 5, 7] = 70000                                   # beyond 16 bits
+    pk = oracle.peaks_count(tab, Cc)
+    v = Cc.astype(np.int64)
+    if n_d0 == 1:
+        mx = ndimage.maximum_filter(v[0], size=3, mode=["constant", "wrap"], cval=-1)[None]
+    else:
+        mx = ndimage.maximum_filter(v, size=3, mode=["constant", "constant", "wrap"], cval=-1)
+    want = np.flatnonzero(((v >= spec["threshold"]) & (v == mx)).ravel())
+    np.testing.assert_array_equal(pk["cell"], want)
+    np.testing.assert_array_equal(pk["count"], Cc.ravel()[want])
+    assert Cc.ravel()[5 * 32 + 7 + 0] == 70000 and (5 * 32 + 7) in pk["cell"]
+
+
+def test_count_peaks_equal_mask_peaks_when_layers_hit_once():
+    # with at most one hit per layer per cell the count of a cell equals the
+    # popcount of its layer mask, so both peak lists coincide
+    spec = synth.grid_spec("c1_single_100trk")
+    spec.update(n_qpt=64, n_phi=128, threshold=6)
+    tab = oracle.Tables(spec)
+    rng = np.random.default_rng(5)
+    layer, phi, _ = synth.track_hits(rng.uniform(-1, 1, 30), rng.uniform(0, 2 * np.pi, 30))
+    Cc = oracle.vote_count(tab, layer, phi)
+    A = oracle.vote_mask(tab, layer, phi)
+    if (Cc == popcount16(A)).all():
+        pc, pm = oracle.peaks_count(tab, Cc), oracle.peaks(tab, A)
+        np.testing.assert_array_equal(pc["cell"], pm["cell"])
+        np.testing.assert_array_equal(pc["count"], pm["popcount"])
+    else:                                                  # two tracks met in a cell
+        assert (Cc >= popcount16(A)).all()
+
+
+def test_count_peaks_hand_cases_and_capacity():
+    spec = tiny_spec(n_qpt=3, n_phi=8, threshold=2)
+    tab = oracle.Tables(spec)
+    Cc = np.zeros((1, 3, 8), np.uint32)
+    Cc[0, 0, 0] = 5                        # row 0, p 0 ...
+    Cc[0, 1, 7] = 5                        # ... ties with its wrapped diagonal neighbour: both peaks
+    Cc[0, 2, 5] = 2                        # at threshold, isolated: peak
+    Cc[0, 2, 4] = 1                        # below threshold
+    Cc[0, 1, 2] = 3                        # loses to (0, 2) above it
+    Cc[0, 0, 2] = 4                        # peak
+    Cc[0, 2, 1] = 2                        # at threshold but (1, 2) = 3 is a diagonal neighbour
+    pk = oracle.peaks_count(tab, Cc)
+    assert pk["cell"].tolist() == [0, 2, 15, 21]
+    assert pk["count"].tolist() == [5, 4, 5, 2]
+    cell = np.zeros(2, np.uint32)
+    cnt = np.zeros(2, np.uint32)
+    import ctypes
+    n = oracle._load().orc_peaks_count(ctypes.byref(tab.cs), oracle._p(Cc.reshape(-1)), oracle._p(cell),
+                                       oracle._p(cnt), 2)
+    assert n == 4 and cell.tolist() == [0, 2]
