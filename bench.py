@@ -349,6 +349,44 @@ def recorded_traffic(name):
     return round(k["bytes_per_launch"]) if source_sha(k["source"]) == k["sha256"] else None
 
 
+def bench_count_form(H, torch, reps=5):
+    """The paper's counting accumulator on its own detector and 2048 x 2048
+    grid: time per event (count vote + count peaks) against the number of
+    tracks, the shape of the paper's Figure 2 (no noise, 0.4 mm hits)."""
+    import synth
+    name = "p6_paper_2048_count"
+    spec = synth.grid_spec(name)
+    cfg = synth.CONFIGS[name]
+    ctx = H.HoughContext(spec, max_events=1, max_hits=1 << 17)
+    cnt = ctx.new_counts(1)
+    cap = ctx.cells
+    pk, poff = ctx.new_peaks(cap), ctx.new_offsets(1)
+    sweep = []
+    for n_tracks in (100, 300, 1000, 3000, 5000):
+        rng = np.random.default_rng(np.random.SeedSequence(0, spawn_key=(cfg["index"], n_tracks)))
+        layer, phi, z, _ = synth.gen_event(cfg, rng, n_tracks=n_tracks)
+        hits = H.DeviceHits.from_batch(synth.concat_events([(layer, phi, z)]))
+        ctx.vote_count(hits, cnt)
+        ctx.peaks_count(cnt, 1, capacity=cap, peaks=pk, offsets=poff)
+        torch.cuda.synchronize()
+        ctx.kernel_times_reset()
+        ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.vote_count(hits, cnt)
+            ctx.peaks_count(cnt, 1, capacity=cap, peaks=pk, offsets=poff)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ctx.set_profiling(False)
+        kt = ctx.kernel_times()
+        sweep.append(dict(tracks=n_tracks, hits=len(layer), ms_per_event=round(dt * 1e3, 4),
+                          votes_per_s=len(layer) * spec["n_qpt"] / dt,
+                          peaks=int(H.offsets_numpy(poff)[-1]),
+                          kernel_ms={k: round(v[1] / v[0], 4) for k, v in kt.items() if v[0]}))
+    return dict(workload=name + ": paper detector (10 layers, r = 11 i cm), 2048 x 2048 counts, "
+                "0.4 mm hits, no noise", sweep=sweep)
+
+
 def cpu_baseline(spec, ev):
     import oracle
     tab = oracle.Tables(spec)
@@ -414,6 +452,11 @@ def main():
         log("c4 batched vs plain ...")
         res["batched"] = bench_batched(H, torch)
         log(f"c4: graph {res['batched']['graph_ms']} ms, plain {res['batched']['plain_ms']} ms")
+    if not args.no_batched:
+        log("paper-detector counting form sweep ...")
+        res["count_form"] = bench_count_form(H, torch)
+        log("count form: " + ", ".join(f"{x['tracks']} trk {x['ms_per_event']} ms"
+                                       for x in res["count_form"]["sweep"]))
     if not args.no_serving:
         from paper_1310_7556_amd import serve
         log("c5 serving sweep ...")

@@ -113,6 +113,12 @@ typedef struct {
     uint16_t popcount;              /* number of layers in the mask */
 } hough_peak;
 
+/* One local maximum of a counting accumulator (hough_peaks_count). */
+typedef struct {
+    uint32_t cell;                  /* (d * n_qpt + k) * n_phi + p within its event */
+    uint32_t count;                 /* the cell's vote count */
+} hough_count_peak;
+
 /* One rz refinement result. */
 typedef struct {
     uint32_t peak;                  /* index of the candidate in its event's peak list */
@@ -173,6 +179,27 @@ int hough_vote(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, void *stre
 int hough_peaks(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events,
                 hough_peak *peaks, uint64_t capacity, uint64_t *event_peak_offsets,
                 void *stream);
+
+/* Step 1 in the paper's counting form (the Discussion's A[B[i]] += 1): for
+ * every event e, every hit h of e with layer l < n_layers and every
+ * reachable row (d, k):
+ *     counts[e][d][k][(phi_h - O[l][d][k]) >> (32 - log2 n_phi)] += 1.
+ * counts: device, n_events * n_d0 * n_qpt * n_phi uint32, fully overwritten.
+ * Each cell counts every hit that falls in it (several hits of one layer
+ * count several times), unlike the layer mask of hough_vote.  Limits and
+ * errors as hough_vote; hits->z_um is not read.  Per-hit LDS atomics (or
+ * global atomics for rows too wide for an LDS tile); tuned by vote_rows,
+ * vote_threads and vote_wgs_per_cu (vote_algo 2 forces global atomics). */
+int hough_vote_count(hough_ctx *ctx, const hough_hits *hits, uint32_t *counts, void *stream);
+
+/* Step 2 on a counting accumulator: a cell of event e is a peak iff its count
+ * is >= threshold and >= the count of each neighbour (same neighbourhood,
+ * periodicity and boundaries as hough_peaks).  Records {cell, count} in
+ * ascending cell order per event into `peaks` (device, `capacity` records);
+ * offsets and capacity overflow as hough_peaks. */
+int hough_peaks_count(hough_ctx *ctx, const uint32_t *counts, uint32_t n_events,
+                      hough_count_peak *peaks, uint64_t capacity, uint64_t *event_peak_offsets,
+                      void *stream);
 
 /* Confirmation: rz refinement of the candidates of each event (needs
  * n_z0 > 0).  Candidates of event e are its peaks in list order, or, when

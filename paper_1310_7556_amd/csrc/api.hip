@@ -289,6 +289,27 @@ int hough_peaks(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events, hough_pe
     return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peaks");
 }
 
+int hough_vote_count(hough_ctx *ctx, const hough_hits *hits, uint32_t *counts, void *stream)
+{
+    if (!ctx || !hits_ok(ctx, hits, false) || (hits->n_events && !counts)) return HOUGH_EINVAL;
+    if (reinterpret_cast<uintptr_t>(counts) & 3) return HOUGH_EINVAL;
+    if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_vote_count(ctx, hits, counts, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_vote_count");
+}
+
+int hough_peaks_count(hough_ctx *ctx, const uint32_t *counts, uint32_t n_events, hough_count_peak *peaks,
+                      uint64_t capacity, uint64_t *event_peak_offsets, void *stream)
+{
+    if (!ctx || !event_peak_offsets || (n_events && !counts) || (capacity && !peaks)) return HOUGH_EINVAL;
+    if (n_events > ctx->lim.max_events) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_peaks_count(ctx, counts, n_events, reinterpret_cast<uint2 *>(peaks), capacity,
+                                            event_peak_offsets, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peaks_count");
+}
+
 int hough_rz_refine(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks,
                     uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
                     uint64_t capacity, uint64_t *event_rz_offsets, void *stream)

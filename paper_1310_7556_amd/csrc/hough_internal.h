@@ -110,6 +110,9 @@ hipError_t launch_bucket_layers(hough_ctx *c, const hough_hits *h, bool with_z, 
 hipError_t launch_bucket_phi(hough_ctx *c, const hough_hits *h, hipStream_t s);
 hipError_t launch_event_order(hough_ctx *c, const hough_hits *h, hipStream_t s);
 hipError_t launch_vote(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
+hipError_t launch_vote_count(hough_ctx *c, const hough_hits *h, uint32_t *counts, hipStream_t s);
+hipError_t launch_peaks_count(hough_ctx *c, const uint32_t *counts, uint32_t n_events, uint2 *peaks,
+                              uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s);
 hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
                         uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s);
 hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,

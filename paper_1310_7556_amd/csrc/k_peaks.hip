@@ -281,6 +281,104 @@ k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uin
     }
 }
 
+// Local maxima of the counting accumulator (the paper's A[B[i]] += 1 form):
+// the rule of k_peaks with the uint32 vote count of a cell in place of its
+// popcount.  Same tiles, halo and ordered compaction; the staged values are
+// the counts themselves; records are {cell, count}.
+template <bool WRITE>
+__global__ void __launch_bounds__(256)
+k_peaks_count(const uint32_t *__restrict__ cnt, uint32_t n_d0, uint32_t n_qpt, uint32_t nphi,
+              uint32_t log2phi, uint32_t rp, uint32_t n_kt, uint32_t thr, uint32_t *__restrict__ tile_counts,
+              const uint64_t *__restrict__ tile_off, uint2 *__restrict__ peaks, uint64_t capacity)
+{
+    HOUGH_DYNAMIC_LDS(uint32_t, val);
+    __shared__ uint32_t wave_cnt[4];
+    const uint32_t t = threadIdx.x, nt = blockDim.x;
+    const uint32_t item = blockIdx.x;
+    const uint32_t per_event = n_d0 * n_kt;
+    const uint32_t e = item / per_event;
+    const uint32_t d = (item % per_event) / n_kt;
+    const uint32_t k0 = (item % n_kt) * rp;
+    const uint32_t nr = min(rp, n_qpt - k0);
+    const uint32_t planes = n_d0 > 1 ? 3 : 1;
+    const uint32_t prow = nr + 2;
+    const uint64_t cells = uint64_t(n_d0) * n_qpt * nphi;
+    const uint32_t *ev = cnt + uint64_t(e) * cells;
+    // absent neighbours stage as 0, which never exceeds a cell's count
+    const uint32_t staged = planes * prow * nphi;
+    for (uint32_t i = t; i < staged; i += nt) {
+        const uint32_t p = i & (nphi - 1);
+        const uint32_t row = i >> log2phi;
+        const uint32_t pl = planes == 1 ? 0 : row / prow;
+        const uint32_t rr = row - pl * prow;
+        const int dd = planes == 3 ? int(d) + int(pl) - 1 : int(d);
+        const int kk = int(k0) + int(rr) - 1;
+        uint32_t v = 0;
+        if (dd >= 0 && dd < int(n_d0) && kk >= 0 && kk < int(n_qpt)) v = ev[(uint64_t(dd) * n_qpt + kk) * nphi + p];
+        val[i] = v;
+    }
+    __syncthreads();
+
+    const uint32_t cp = planes == 3 ? 1 : 0;
+    const uint32_t ncell = nr * nphi;
+    const uint32_t lane = t & 63, wave = t >> 6, nwaves = nt >> 6;
+    uint32_t count = 0;
+    uint64_t running = WRITE ? tile_off[item] : 0;
+    for (uint32_t base = 0; base < ncell; base += nt) {
+        const uint32_t cidx = base + t;
+        bool is_peak = false;
+        uint32_t rr = 0, p = 0, v = 0;
+        if (cidx < ncell) {
+            rr = cidx >> log2phi;
+            p = cidx & (nphi - 1);
+            const uint32_t pm = (p - 1) & (nphi - 1), pp = (p + 1) & (nphi - 1);
+            v = val[(cp * prow + rr + 1) * nphi + p];
+            if (v >= thr) {
+                bool ok = true;
+                for (uint32_t pl = 0; pl < planes && ok; ++pl) {
+                    for (uint32_t dr = 0; dr < 3; ++dr) {
+                        const uint32_t *row = val + (pl * prow + rr + dr) * nphi;
+                        const bool centre_row = pl == cp && dr == 1;
+                        ok &= row[pm] <= v && row[pp] <= v && (centre_row || row[p] <= v);
+                    }
+                }
+                is_peak = ok;
+            }
+        }
+        if (!WRITE) {
+            count += is_peak;
+            continue;
+        }
+        const uint64_t bal = __ballot(is_peak);
+        const uint32_t before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (uint32_t w = 0; w < nwaves; ++w) {
+            const uint32_t x = wave_cnt[w];
+            woff += w < wave ? x : 0;
+            total += x;
+        }
+        if (is_peak) {
+            const uint64_t pos = running + woff + before;
+            if (pos < capacity)
+                peaks[pos] = make_uint2(uint32_t((uint64_t(d) * n_qpt + k0 + rr) * nphi + p), v);
+        }
+        running += total;
+        __syncthreads();
+    }
+    if (!WRITE) {
+        for (uint32_t off = 32; off > 0; off >>= 1) count += __shfl_down(count, off, 64);
+        if (lane == 0) wave_cnt[wave] = count;
+        __syncthreads();
+        if (t == 0) {
+            uint32_t s = 0;
+            for (uint32_t w = 0; w < nwaves; ++w) s += wave_cnt[w];
+            tile_counts[item] = s;
+        }
+    }
+}
+
 namespace {
 
 constexpr uint32_t kPeakThreads = 256;
@@ -348,6 +446,36 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
         hipLaunchKernelGGL(k_peaks<true>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
                            c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
                            c->d_tile_counts, c->d_tile_off, peaks, capacity);
+    prof_end(c, s, &t);
+    return hipGetLastError();
+}
+
+hipError_t launch_peaks_count(hough_ctx *c, const uint32_t *counts, uint32_t n_events, uint2 *peaks,
+                              uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s)
+{
+    hipError_t err;
+    const uint32_t planes = c->spec.n_d0 > 1 ? 3 : 1;
+    uint32_t rp = std::min(peak_rows(c), c->spec.n_qpt);
+    while (rp > 0 && size_t(planes) * (rp + 2) * c->spec.n_phi * 4 > c->max_lds) --rp;
+    if (rp == 0) return hipErrorInvalidConfiguration;
+    const uint32_t n_kt = (c->spec.n_qpt + rp - 1) / rp;
+    const uint64_t n_items = uint64_t(n_events) * c->spec.n_d0 * n_kt;
+    if (n_events == 0) return launch_scan_counts(c, c->d_tile_counts, 0, c->d_tile_off, 1, event_peak_offsets, s);
+    const size_t lds = size_t(planes) * (rp + 2) * c->spec.n_phi * 4;
+    KernelTimer t;
+    prof_begin(c, "peaks_count_form", s, &t);
+    hipLaunchKernelGGL(k_peaks_count<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, counts,
+                       c->spec.n_d0, c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
+                       c->d_tile_counts, c->d_tile_off, peaks, capacity);
+    prof_end(c, s, &t);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = launch_scan_counts(c, c->d_tile_counts, n_items, c->d_tile_off, uint64_t(c->spec.n_d0) * n_kt,
+                                  event_peak_offsets, s)) != hipSuccess)
+        return err;
+    prof_begin(c, "peaks_write_count_form", s, &t);
+    hipLaunchKernelGGL(k_peaks_count<true>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, counts,
+                       c->spec.n_d0, c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
+                       c->d_tile_counts, c->d_tile_off, peaks, capacity);
     prof_end(c, s, &t);
     return hipGetLastError();
 }

@@ -22,9 +22,11 @@ EXPORTED = [
     "hough_check_spec", "hough_build_tables", "hough_set_tuning", "hough_get_tuning",
     "hough_set_profiling", "hough_kernel_times", "hough_kernel_times_reset",
     "hough_strerror", "hough_last_error", "hough_device_cus", "hough_gather_events",
+    "hough_vote_count", "hough_peaks_count",
 ]
 
 PEAK_DTYPE = np.dtype([("cell", np.uint32), ("mask", np.uint16), ("popcount", np.uint16)])
+COUNT_PEAK_DTYPE = np.dtype([("cell", np.uint32), ("count", np.uint32)])
 RZ_DTYPE = np.dtype([("peak", np.uint32), ("cot_bin", np.uint16), ("z0_bin", np.uint16),
                      ("count", np.uint32), ("n_members", np.uint32)])
 
@@ -90,6 +92,8 @@ def load_library():
         "hough_last_error": ([P], C.c_char_p),
         "hough_device_cus": ([P], i32),
         "hough_gather_events": ([P, P, P, P, P, P, u32, P, P, P, P], i32),
+        "hough_vote_count": ([P, P, P, P], i32),
+        "hough_peaks_count": ([P, P, u32, P, u64, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -285,6 +289,31 @@ class HoughContext:
                                     _stream(stream)), self._h, "hough_peaks")
         return peaks, offsets
 
+    def new_counts(self, n_events):
+        """Counting accumulator: int32 tensor holding uint32 counts."""
+        torch = _torch()
+        return torch.empty((n_events, self.spec["n_d0"], self.spec["n_qpt"], self.spec["n_phi"]),
+                           dtype=torch.int32, device=f"cuda:{self.device}")
+
+    def vote_count(self, hits, counts=None, stream=None):
+        if counts is None:
+            counts = self.new_counts(hits.n_events)
+        h = hits.struct()
+        _check(self.lib.hough_vote_count(self._h, C.byref(h), _ptr(counts), _stream(stream)), self._h,
+               "hough_vote_count")
+        return counts
+
+    def peaks_count(self, counts, n_events, capacity=None, peaks=None, offsets=None, stream=None):
+        if capacity is None:
+            capacity = n_events * self.cells
+        if peaks is None:
+            peaks = self.new_peaks(capacity)
+        if offsets is None:
+            offsets = self.new_offsets(n_events)
+        _check(self.lib.hough_peaks_count(self._h, _ptr(counts), n_events, _ptr(peaks), capacity,
+                                          _ptr(offsets), _stream(stream)), self._h, "hough_peaks_count")
+        return peaks, offsets
+
     def rz_refine(self, hits, peaks, peak_offsets, peak_capacity=None, capacity=None, out=None,
                   offsets=None, stream=None):
         if peak_capacity is None:
@@ -367,6 +396,20 @@ def peaks_numpy(peaks, offsets, event=None):
     n = int(off[-1])
     cap = peaks.shape[0]
     arr = peaks[:min(n, cap)].cpu().numpy().view(PEAK_DTYPE).reshape(-1)
+    if event is None:
+        return arr
+    return arr[int(off[event]):int(off[event + 1])]
+
+
+def counts_numpy(counts):
+    return counts.cpu().numpy().view(np.uint32)
+
+
+def count_peaks_numpy(peaks, offsets, event=None):
+    """Count-peak records (all events, or one) as a COUNT_PEAK_DTYPE array."""
+    off = offsets_numpy(offsets)
+    n = int(off[-1])
+    arr = peaks[:min(n, peaks.shape[0])].cpu().numpy().view(COUNT_PEAK_DTYPE).reshape(-1)
     if event is None:
         return arr
     return arr[int(off[event]):int(off[event + 1])]
