@@ -246,7 +246,8 @@ def bench_batched(H, torch, reps=5):
                       bytes_per_launch=vote_bytes),
         vote_stage=dict(kernels_ms=round(t_stage * 1e3, 4), bytes=stage_bytes,
                         achieved_gbs=round(stage_bytes / t_stage / 1e9, 2),
-                        frac=round(stage_bytes / t_stage / 1e9 / HBM_PEAK_GBS, 5)))
+                        frac=round(stage_bytes / t_stage / 1e9 / HBM_PEAK_GBS, 5)),
+        vote_alu=vote_alu_view(vk, E * ctx.cells, spec["n_layers"], t_vote))
 
 
 # --- HBM traffic of the dominant kernels ---------------------------------
@@ -349,6 +350,25 @@ def recorded_traffic(name):
     return round(k["bytes_per_launch"]) if source_sha(k["source"]) == k["sha256"] else None
 
 
+# The direct vote decides every (cell, layer) pair with three VALU
+# instructions per 64 decisions (subtract, subtract with borrow, add with
+# carry): its own ALU roof, beside the HBM one.
+DIRECT_VALU_PER_64_DECISIONS = 3
+
+
+def vote_alu_view(kernel, cells, layers, seconds):
+    """ALU roofline of the direct vote: cells x layers decisions per launch."""
+    if kernel != "vote_direct":
+        return None
+    decisions = cells * layers
+    ops = decisions * DIRECT_VALU_PER_64_DECISIONS       # lane operations
+    alu_floor = ops / (ALU_PEAK_TOPS * 1e12)
+    return dict(decisions_per_launch=decisions, lane_ops_per_decision=DIRECT_VALU_PER_64_DECISIONS,
+                achieved_tops=round(ops / seconds / 1e12, 3), peak_tops=round(ALU_PEAK_TOPS, 2),
+                frac=round(alu_floor / seconds, 5), alu_floor_ms=round(alu_floor * 1e3, 4),
+                hbm_floor_ms=round(2 * cells / (HBM_PEAK_GBS * 1e9) * 1e3, 4))
+
+
 def bench_count_form(H, torch, reps=5):
     """The paper's counting accumulator on its own detector and 2048 x 2048
     grid: time per event (count vote + count peaks) against the number of
@@ -385,6 +405,35 @@ def bench_count_form(H, torch, reps=5):
                           kernel_ms={k: round(v[1] / v[0], 4) for k, v in kt.items() if v[0]}))
     return dict(workload=name + ": paper detector (10 layers, r = 11 i cm), 2048 x 2048 counts, "
                 "0.4 mm hits, no noise", sweep=sweep)
+
+
+def _oracle_event(args):
+    spec, layer, phi = args
+    import oracle
+    tab = oracle.Tables(spec)
+    A = oracle.vote_mask(tab, layer, phi)
+    oracle.peaks(tab, A)
+    return len(layer)
+
+
+def cpu_baseline_batched(n_events=64):
+    """The oracle on a sample of the 4096-event batch, one event per worker
+    process across the host cores (vote and peaks, as in the batched path)."""
+    import multiprocessing as mp
+    import synth
+    name = "c4_batch_4096"
+    spec = synth.grid_spec(name)
+    batch = synth.gen_batch(name, n_events)
+    work = [(spec, batch.event(e).layer, batch.event(e).phi) for e in range(n_events)]
+    cores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        hits = sum(pool.map(_oracle_event, work, chunksize=1))
+    dt = time.perf_counter() - t0
+    return dict(value=hits * spec["n_qpt"] / dt, unit="votes/s", events_per_s=n_events / dt, cores=cores,
+                kind="oracle", seconds=round(dt, 2),
+                sample=f"the first {n_events} events of the 4096-event batch ({hits} hits): vote and peaks, "
+                       f"one event per process on {cores} host cores (pool start-up included)")
 
 
 def cpu_baseline(spec, ev):
@@ -464,6 +513,9 @@ def main():
     if not args.no_cpu:
         log("cpu oracle baseline ...")
         res["cpu_baseline"] = cpu_baseline(spec, ev)
+        if not args.no_batched:
+            log("cpu oracle baseline, batched sample ...")
+            res["batched"]["cpu_baseline"] = cpu_baseline_batched()
     print(json.dumps(res))
 
 
