@@ -59,6 +59,8 @@ def _load():
         lib.orc_rz.argtypes = [P, P, P, P, C.c_uint64, P, P, P, C.c_uint64, P, P,
                                P, P, P, P, P]
         lib.orc_rz.restype = C.c_uint64
+        lib.orc_clusters.argtypes = [P, C.c_uint64, P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_clusters.restype = C.c_uint64
         _lib = lib
     return _lib
 
@@ -196,6 +198,43 @@ def rz(tab, layer, phi, z, pk):
     out["peak"], out["cot_bin"], out["z0_bin"] = op[:m], oc[:m], oz[:m]
     out["count"], out["n_members"] = on[:m], om[:m]
     return out
+
+
+CLUSTER_DTYPE = np.dtype([("first", np.uint32), ("n_peaks", np.uint32), ("sum_dd", np.int32),
+                          ("sum_dk", np.int32), ("sum_dp", np.int32), ("popcount", np.uint16),
+                          ("mask_or", np.uint16)])
+
+
+def clusters(tab, pk):
+    """Plateau clusters of one event's peak list (connected components of
+    adjacent peak cells, phi0 periodic): (label per peak, cluster records in
+    the order of their first peak)."""
+    cell = np.ascontiguousarray(pk["cell"], np.uint32)
+    mask = np.ascontiguousarray(pk["mask"], np.uint16)
+    pc = np.ascontiguousarray(pk["popcount"], np.uint16)
+    n = len(cell)
+    label = np.zeros(n + 1, np.uint32)
+    a = [np.zeros(n + 1, t) for t in (np.uint32, np.uint32, np.int32, np.int32, np.int32,
+                                      np.uint16, np.uint16)]
+    m = _load().orc_clusters(C.byref(tab.cs), n, _p(cell), _p(mask), _p(pc), _p(label),
+                             *[_p(x) for x in a])
+    out = np.zeros(m, CLUSTER_DTYPE)
+    for name, x in zip(CLUSTER_DTYPE.names, a):
+        out[name] = x[:m]
+    return label[:n], out
+
+
+def cluster_centroids(tab, pk, cl):
+    """Centroid bin coordinates (d, k, p) of each cluster, fp64, p in
+    [0, n_phi): the first peak's bin plus the mean member offset."""
+    s = tab.spec
+    np_, nk = s["n_phi"], s["n_qpt"]
+    f = pk["cell"][cl["first"]].astype(np.int64)
+    n = cl["n_peaks"].astype(np.float64)
+    d = f // (np_ * nk) + cl["sum_dd"] / n
+    k = (f // np_) % nk + cl["sum_dk"] / n
+    p = np.mod(f % np_ + cl["sum_dp"] / n, np_)
+    return d, k, p
 
 
 def run_event(tab, layer, phi, z=None, with_rz=None):

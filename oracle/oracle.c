@@ -351,3 +351,90 @@ uint64_t orc_rz(const orc_spec *g, const uint32_t *O, const uint8_t *V, const in
     free(cand); free(mem); free(hist); free(bins);
     return n_cand;
 }
+
+/* ---- candidate confirmation: plateau clusters --------------------------
+ *
+ * The non-strict local-maximum rule reports every cell of a flat-topped
+ * ridge, so one track can give several adjacent peaks (Section 3 leaves the
+ * confirmation of candidates to more expensive later computations).  Two
+ * peaks of one event are adjacent when their cells are neighbours in the
+ * local-maximum neighbourhood (3x3 in (q/pT, phi0), 3x3x3 with a d0 axis;
+ * phi0 periodic, q/pT and d0 not).  A cluster is a connected component of
+ * that adjacency relation over the event's peak list.
+ *
+ * Clusters are numbered in the order of their first peak (the member with
+ * the smallest list index, hence the smallest cell); label[i] is peak i's
+ * cluster number.  Per cluster: first, n_peaks, and the sums over its
+ * members of d - d_first, k - k_first and the signed phi0 offset
+ * ((p - p_first) mod n_phi, taken in [-n_phi/2, n_phi/2)); popcount of the
+ * first peak and the OR of the members' masks.  The centroid is
+ * (d_first + sum_dd / n, k_first + sum_dk / n, p_first + sum_dp / n mod n_phi).
+ * Found by breadth-first search from each unlabelled peak in list order over
+ * a dense cell -> peak map.  Returns the number of clusters; every output
+ * array is sized by the caller for n entries. */
+uint64_t orc_clusters(const orc_spec *g, uint64_t n, const uint32_t *cell, const uint16_t *mask,
+                      const uint16_t *pc, uint32_t *label, uint32_t *first, uint32_t *n_peaks,
+                      int32_t *sum_dd, int32_t *sum_dk, int32_t *sum_dp, uint16_t *cl_pc,
+                      uint16_t *cl_mask)
+{
+    int nd = (int)g->n_d0, nk = (int)g->n_qpt, np = (int)g->n_phi;
+    size_t cells = (size_t)nd * nk * np;
+    int64_t *at = (int64_t *)malloc(cells * sizeof(int64_t));
+    uint32_t *queue = (uint32_t *)malloc((n + 1) * sizeof(uint32_t));
+    for (size_t c = 0; c < cells; c++) at[c] = -1;
+    for (uint64_t i = 0; i < n; i++) {
+        at[cell[i]] = (int64_t)i;
+        label[i] = 0xFFFFFFFFu;
+    }
+    uint64_t n_cl = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        if (label[i] != 0xFFFFFFFFu) continue;
+        uint32_t id = (uint32_t)n_cl++;
+        first[id] = (uint32_t)i;
+        label[i] = id;
+        uint64_t head = 0, tail = 0;
+        queue[tail++] = (uint32_t)i;
+        while (head < tail) {
+            uint32_t x = queue[head++];
+            int p = (int)(cell[x] % (uint32_t)np);
+            int k = (int)((cell[x] / (uint32_t)np) % (uint32_t)nk);
+            int d = (int)(cell[x] / ((uint32_t)np * (uint32_t)nk));
+            for (int dd = -1; dd <= 1; dd++) {
+                int d2 = d + dd;
+                if (d2 < 0 || d2 >= nd) continue;
+                for (int dk = -1; dk <= 1; dk++) {
+                    int k2 = k + dk;
+                    if (k2 < 0 || k2 >= nk) continue;
+                    for (int dp = -1; dp <= 1; dp++) {
+                        int p2 = ((p + dp) % np + np) % np;
+                        int64_t y = at[((size_t)d2 * nk + k2) * np + p2];
+                        if (y < 0 || label[y] != 0xFFFFFFFFu) continue;
+                        label[y] = id;
+                        queue[tail++] = (uint32_t)y;
+                    }
+                }
+            }
+        }
+    }
+    for (uint64_t c = 0; c < n_cl; c++) {
+        n_peaks[c] = 0;
+        sum_dd[c] = sum_dk[c] = sum_dp[c] = 0;
+        cl_pc[c] = pc[first[c]];
+        cl_mask[c] = 0;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t c = label[i], f = cell[first[c]];
+        int p = (int)(cell[i] % (uint32_t)np), pf = (int)(f % (uint32_t)np);
+        int k = (int)((cell[i] / (uint32_t)np) % (uint32_t)nk), kf = (int)((f / (uint32_t)np) % (uint32_t)nk);
+        int d = (int)(cell[i] / ((uint32_t)np * (uint32_t)nk)), df = (int)(f / ((uint32_t)np * (uint32_t)nk));
+        int dp = ((p - pf) % np + np) % np;
+        if (dp >= np / 2) dp -= np;
+        n_peaks[c]++;
+        sum_dd[c] += d - df;
+        sum_dk[c] += k - kf;
+        sum_dp[c] += dp;
+        cl_mask[c] |= mask[i];
+    }
+    free(at); free(queue);
+    return n_cl;
+}

@@ -534,3 +534,162 @@ def test_count_peaks_hand_cases_and_capacity():
     n = oracle._load().orc_peaks_count(ctypes.byref(tab.cs), oracle._p(Cc.reshape(-1)), oracle._p(cell),
                                        oracle._p(cnt), 2)
     assert n == 4 and cell.tolist() == [0, 2]
+
+
+# --------------------------------------------------------------------------
+# Candidate confirmation: plateau clusters of adjacent peaks
+# --------------------------------------------------------------------------
+
+def peak_list(A, cells):
+    """Peak records for the given cells of A (any cells: the clustering
+    does not re-check the local-maximum rule)."""
+    cells = np.sort(np.asarray(cells, np.int64))
+    pk = np.zeros(len(cells), oracle.PEAK_DTYPE)
+    pk["cell"] = cells
+    pk["mask"] = A.ravel()[cells]
+    pk["popcount"] = popcount16(A).ravel()[cells]
+    return pk
+
+
+def _random_image(rng, shape, density):
+    img = rng.random(shape) < density
+    c0 = int(rng.integers(shape[-1]))
+    img[..., c0] = False                       # an empty phi0 column
+    return img, c0
+
+
+@pytest.mark.parametrize("n_d0,density,seed", [(1, 0.25, 0), (1, 0.35, 1), (1, 0.6, 2),
+                                                (3, 0.15, 3), (3, 0.25, 4)])
+def test_clusters_match_ndimage_label(n_d0, density, seed):
+    # With an empty phi0 column rolled to the array edge no adjacency crosses
+    # the edge, so scipy's non-periodic labelling with full connectivity gives
+    # exactly the periodic components.
+    rng = np.random.default_rng(seed)
+    spec = tiny_spec(n_qpt=20, n_phi=32, n_d0=n_d0, d0=(-50.0, 50.0), threshold=1)
+    tab = oracle.Tables(spec)
+    img, c0 = _random_image(rng, (n_d0, 20, 32), density)
+    A = (rng.integers(1, 1 << 10, img.shape) * img).astype(np.uint16)
+    pk = peak_list(A, np.flatnonzero(img.ravel()))
+    lab, cl = oracle.clusters(tab, pk)
+    rolled = np.roll(img, -c0, axis=-1)
+    ref, n_ref = ndimage.label(rolled if n_d0 > 1 else rolled[0],
+                               structure=np.ones((3,) * (3 if n_d0 > 1 else 2)))
+    ref = np.roll(ref.reshape(img.shape), c0, axis=-1).ravel()[pk["cell"]]
+    assert len(cl) == n_ref
+    pairs = set(zip(lab.tolist(), ref.tolist()))
+    assert len(pairs) == n_ref                  # one-to-one between the two labellings
+    # numbering: by first peak, which is the smallest index carrying the label
+    assert np.all(np.diff(cl["first"].astype(np.int64)) > 0)
+    first_idx = np.array([np.flatnonzero(lab == c)[0] for c in range(len(cl))])
+    np.testing.assert_array_equal(cl["first"], first_idx)
+    np.testing.assert_array_equal(cl["n_peaks"], np.bincount(lab, minlength=len(cl)))
+    # OR of masks and the first peak's popcount
+    for c in range(len(cl)):
+        assert cl["mask_or"][c] == np.bitwise_or.reduce(pk["mask"][lab == c])
+    np.testing.assert_array_equal(cl["popcount"], pk["popcount"][cl["first"]])
+    # centroids against scipy's centre of mass in the rolled frame, for
+    # clusters narrower than half the phi0 period
+    D, K, P = oracle.cluster_centroids(tab, pk, cl)
+    rl, _ = ndimage.label(rolled, structure=np.ones((3, 3, 3)) if n_d0 > 1 else
+                          np.pad(np.ones((1, 3, 3)), ((1, 1), (0, 0), (0, 0))))
+    idx = np.arange(1, n_ref + 1)
+    com = np.array(ndimage.center_of_mass(rolled.astype(float), rl, idx))
+    ext = [s[-1].stop - s[-1].start for s in ndimage.find_objects(rl)]
+    rcell = pk["cell"][cl["first"]]
+    rpos = np.array(np.unravel_index(rcell, img.shape)).T
+    rpos[:, 2] = (rpos[:, 2] - c0) % 32
+    rlab = rl[tuple(rpos.T)]                    # scipy label of each cluster's first peak
+    checked = 0
+    for c in range(len(cl)):
+        j = rlab[c] - 1
+        if ext[j] >= 16:
+            continue
+        checked += 1
+        assert D[c] == pytest.approx(com[j][0], abs=1e-12)
+        assert K[c] == pytest.approx(com[j][1], abs=1e-12)
+        assert (P[c] - c0) % 32 == pytest.approx(com[j][2], abs=1e-9)
+    assert checked >= len(cl) // 2
+
+
+def test_clusters_hand_cases():
+    spec = tiny_spec(n_qpt=4, n_phi=8, threshold=1)
+    tab = oracle.Tables(spec)
+    A = np.zeros((1, 4, 8), np.uint16)
+    cells = [(0, 0), (0, 7),                   # wrap neighbours in phi0: one cluster
+             (1, 3),                           # diagonal of nothing: alone
+             (2, 5), (3, 6),                   # diagonal pair
+             (3, 0)]                           # kappa does not wrap: (0, 0) is no neighbour
+    for k, p in cells:
+        A[0, k, p] = 0x7
+    A[0, 0, 7] = 0x38
+    pk = peak_list(A, [k * 8 + p for k, p in cells])
+    lab, cl = oracle.clusters(tab, pk)
+    # list order: 0, 7, 11, 21, 24, 30
+    assert lab.tolist() == [0, 0, 1, 2, 3, 2]
+    assert cl["first"].tolist() == [0, 2, 3, 4]
+    assert cl["n_peaks"].tolist() == [2, 1, 2, 1]
+    assert cl["sum_dp"].tolist() == [-1, 0, 1, 0]  # (0,7) is one step below (0,0)
+    assert cl["sum_dk"].tolist() == [0, 0, 1, 0]
+    assert cl["mask_or"].tolist() == [0x3F, 0x7, 0x7, 0x7]
+    _, _, P = oracle.cluster_centroids(tab, pk, cl)
+    assert P[0] == pytest.approx(7.5)          # centroid across the wrap
+
+
+def test_clusters_two_phi_bins_and_d0_axis():
+    # n_phi = 2: both phi0 neighbours are the same cell
+    spec = tiny_spec(n_qpt=3, n_phi=2, threshold=1)
+    tab = oracle.Tables(spec)
+    A = np.full((1, 3, 2), 1, np.uint16)
+    lab, cl = oracle.clusters(tab, peak_list(A, [0, 1, 5]))
+    assert lab.tolist() == [0, 0, 1] and cl["sum_dp"].tolist() == [-1, 0]
+    # d0 axis: (d, k, p) and (d + 1, k + 1, p - 1) touch; d does not wrap
+    spec = tiny_spec(n_qpt=3, n_phi=4, n_d0=3, d0=(-30.0, 30.0), threshold=1)
+    tab = oracle.Tables(spec)
+    A = np.full((3, 3, 4), 1, np.uint16)
+    c = lambda d, k, p: (d * 3 + k) * 4 + p
+    lab, cl = oracle.clusters(tab, peak_list(A, [c(0, 0, 0), c(1, 1, 3), c(2, 0, 0)]))
+    assert lab.tolist() == [0, 0, 0] and cl["sum_dd"].tolist() == [3]
+    lab, cl = oracle.clusters(tab, peak_list(A, [c(0, 1, 1), c(2, 1, 1)]))
+    assert lab.tolist() == [0, 1]
+
+
+@pytest.mark.parametrize("name,cells", [
+    ("c1_single_100trk", [(128, 17), (77, 201), (40, 255)]),
+    ("c2_single_1ktrk_rz", [(512, 1023), (300, 0)]),
+])
+def test_clusters_merge_a_bin_centre_ridge(name, cells):
+    # One noiseless bin-centre track leaves a ridge of equal full-layer peaks
+    # along q/pT; away from the q/pT edges the ridge is symmetric about the
+    # track's bin, so it becomes one cluster whose centroid is that bin.
+    spec = synth.grid_spec(name)
+    tab = oracle.Tables(spec)
+    K, N = spec["n_qpt"], spec["n_phi"]
+    kap = centres(spec["qpt_lo"], spec["qpt_hi"], K)
+    for k, p in cells:
+        layer, phi, _ = synth.track_hits(kap[k], (p + 0.5) / N * 2 * math.pi)
+        pk = oracle.peaks(tab, oracle.vote_mask(tab, layer, phi))
+        assert len(pk) > 1
+        lab, cl = oracle.clusters(tab, pk)
+        assert len(cl) == 1 and cl["popcount"][0] == 10 and cl["mask_or"][0] == 0x3FF
+        _, kc, pc = oracle.cluster_centroids(tab, pk, cl)
+        assert kc[0] == k and pc[0] == p
+
+
+def test_clusters_of_real_peaks_are_equal_valued_and_separated():
+    # Adjacent local maxima are each >= the other, so a cluster's members
+    # share one popcount; members of different clusters are never adjacent.
+    spec = tiny_spec(n_qpt=32, n_phi=64, threshold=4)
+    tab = oracle.Tables(spec)
+    rng = np.random.default_rng(5)
+    layer, phi, _ = random_hits(rng, 300)
+    pk = oracle.peaks(tab, oracle.vote_mask(tab, layer, phi))
+    lab, cl = oracle.clusters(tab, pk)
+    assert len(cl) < len(pk)
+    np.testing.assert_array_equal(pk["popcount"], cl["popcount"][lab])
+    k = pk["cell"] // 64
+    p = pk["cell"] % 64
+    dk = np.abs(k[:, None].astype(int) - k[None, :])
+    dp = np.abs(p[:, None].astype(int) - p[None, :])
+    adj = (dk <= 1) & (np.minimum(dp, 64 - dp) <= 1)
+    same = lab[:, None] == lab[None, :]
+    assert not np.any(adj & ~same)
