@@ -92,7 +92,9 @@ typedef struct {
 typedef struct {
     uint32_t max_events;            /* events per call, >= 1 */
     uint64_t max_hits;              /* hits per call (all events), < 2^32 */
-    uint64_t max_peaks;             /* reserved (peak buffers are the caller's); may be 0 */
+    uint64_t max_peaks;             /* largest peak_capacity hough_peak_clusters accepts (< 2^32;
+                                       the context keeps 4 bytes of scratch per peak); 0 when
+                                       that call is not used */
 } hough_limits;
 
 /* Hits of n_events events, concatenated (structure of arrays). */
@@ -126,6 +128,22 @@ typedef struct {
     uint32_t count;                 /* member votes in that (cot, z0) bin */
     uint32_t n_members;             /* hits that voted into the candidate's cell */
 } hough_rz;
+
+/* One plateau cluster (hough_peak_clusters).  Offsets are taken from the
+ * cluster's first peak (d_f, k_f, p_f); the centroid in bin coordinates is
+ * (d_f + sum_dd / n_peaks, k_f + sum_dk / n_peaks, p_f + sum_dp / n_peaks
+ * modulo n_phi).  24 bytes, 8-byte aligned arrays. */
+typedef struct {
+    uint32_t first;                 /* index in its event's peak list of the member with the
+                                       smallest cell */
+    uint16_t popcount;              /* the members' popcount (adjacent local maxima are equal) */
+    uint16_t mask_or;               /* OR of the members' layer masks */
+    uint32_t n_peaks;               /* members */
+    int32_t  sum_dk;                /* sum over members of k - k_f */
+    int32_t  sum_dp;                /* sum over members of (p - p_f) mod n_phi, taken in
+                                       [-n_phi/2, n_phi/2) */
+    int32_t  sum_dd;                /* sum over members of d - d_f */
+} hough_cluster;
 
 /* Autotuning knobs of the kernels (all 0 = library default). */
 typedef struct {
@@ -200,6 +218,26 @@ int hough_vote_count(hough_ctx *ctx, const hough_hits *hits, uint32_t *counts, v
 int hough_peaks_count(hough_ctx *ctx, const uint32_t *counts, uint32_t n_events,
                       hough_count_peak *peaks, uint64_t capacity, uint64_t *event_peak_offsets,
                       void *stream);
+
+/* Candidate confirmation, plateau de-duplication.  The local-maximum rule
+ * is non-strict, so a flat-topped ridge of votes gives several adjacent
+ * peaks (Section 3 leaves the confirmation of candidates to later, more
+ * expensive steps).  Two peaks of one event are adjacent when their cells
+ * are neighbours in the local-maximum neighbourhood (3x3, 3x3x3 with a d0
+ * axis; phi0 periodic, q/pT and d0 not); a cluster is a connected component
+ * of that relation.  Clusters of event e are numbered in the order of their
+ * first peak and written to clusters[coff[e] ...] (device, `capacity`
+ * records, 8-byte aligned), coff = event_cluster_offsets (device, n_events +
+ * 1 uint64, written by the call); overflow is handled as in hough_peaks.
+ * peak_cluster (device, peak_capacity uint32, 4-byte aligned) receives for
+ * every stored peak its cluster's index within the event.  peaks (8-byte
+ * aligned) and event_peak_offsets are hough_peaks' outputs for n_events
+ * events; peaks it dropped for lack of capacity are not seen.  Requires
+ * peak_capacity <= max_peaks (HOUGH_ELIMIT). */
+int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_capacity,
+                        const uint64_t *event_peak_offsets, uint32_t n_events, uint32_t *peak_cluster,
+                        hough_cluster *clusters, uint64_t capacity, uint64_t *event_cluster_offsets,
+                        void *stream);
 
 /* Confirmation: rz refinement of the candidates of each event (needs
  * n_z0 > 0).  Candidates of event e are its peaks in list order, or, when

@@ -50,7 +50,8 @@ void free_all(hough_ctx *c)
     void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
                     c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list,
-                    c->d_scan_part, c->d_scan_off, c->d_dir_tab};
+                    c->d_scan_part, c->d_scan_off, c->d_dir_tab, c->d_cl_rank, c->d_cl_part,
+                    c->d_cl_part_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : c->pending) {
@@ -165,7 +166,8 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     if (!out) return HOUGH_EINVAL;
     *out = nullptr;
     if (!spec || !limits || !spec_valid(*spec)) return HOUGH_EINVAL;
-    if (limits->max_events < 1 || limits->max_hits >= (uint64_t(1) << 32)) return HOUGH_EINVAL;
+    if (limits->max_events < 1 || limits->max_hits >= (uint64_t(1) << 32) || limits->max_peaks >= (uint64_t(1) << 32))
+        return HOUGH_EINVAL;
     int n_dev = 0;
     if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return HOUGH_EINVAL;
     DeviceGuard guard(device);
@@ -236,7 +238,10 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
               dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh) &&
               dev_alloc(&c->d_gap_info, size_t(E) * L) && dev_alloc(&c->d_gap_list, H) &&
               dev_alloc(&c->d_scan_part, c->scan_blocks_max) && dev_alloc(&c->d_scan_off, c->scan_blocks_max + 1) &&
-              dev_alloc(&c->d_dir_tab, size_t(E) * L * spec->n_phi);
+              dev_alloc(&c->d_dir_tab, size_t(E) * L * spec->n_phi) &&
+              dev_alloc(&c->d_cl_rank, limits->max_peaks) &&
+              dev_alloc(&c->d_cl_part, cluster_blocks(limits->max_peaks)) &&
+              dev_alloc(&c->d_cl_part_off, cluster_blocks(limits->max_peaks) + 1);
     if (!ok) {
         free_all(c);
         delete c;
@@ -308,6 +313,24 @@ int hough_peaks_count(hough_ctx *ctx, const uint32_t *counts, uint32_t n_events,
     const hipError_t e = launch_peaks_count(ctx, counts, n_events, reinterpret_cast<uint2 *>(peaks), capacity,
                                             event_peak_offsets, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peaks_count");
+}
+
+int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_capacity,
+                        const uint64_t *event_peak_offsets, uint32_t n_events, uint32_t *peak_cluster,
+                        hough_cluster *clusters, uint64_t capacity, uint64_t *event_cluster_offsets,
+                        void *stream)
+{
+    if (!ctx || !event_peak_offsets || !event_cluster_offsets || (peak_capacity && (!peaks || !peak_cluster)) ||
+        (capacity && !clusters))
+        return HOUGH_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(peaks) & 7) || (reinterpret_cast<uintptr_t>(clusters) & 7) ||
+        (reinterpret_cast<uintptr_t>(peak_cluster) & 3))
+        return HOUGH_EINVAL;
+    if (n_events > ctx->lim.max_events || peak_capacity > ctx->lim.max_peaks) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_clusters(ctx, peaks, peak_capacity, event_peak_offsets, n_events, peak_cluster,
+                                         clusters, capacity, event_cluster_offsets, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peak_clusters");
 }
 
 int hough_rz_refine(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks,

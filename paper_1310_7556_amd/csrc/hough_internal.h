@@ -87,6 +87,9 @@ struct hough_ctx {
     uint2 *d_dir_tab = nullptr;        // [max_events][L][n_phi] direct vote: per-bucket {lo, span}
     size_t max_lds_direct = 65536;     // LDS budget of the direct vote's table staging
     uint64_t n_peak_tiles = 0;
+    uint32_t *d_cl_rank = nullptr;     // [max_peaks] plateau clusters: cluster index of each root
+    uint32_t *d_cl_part = nullptr;     // [cluster blocks] roots per block of the peak list
+    uint64_t *d_cl_part_off = nullptr; // [cluster blocks + 1] their exclusive prefix
 
     // profiling
     bool prof = false;
@@ -136,6 +139,11 @@ uint64_t scan_blocks(uint64_t n);
 hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
                               uint64_t stride_out, uint64_t *out_strided, hipStream_t s);
 
+// Plateau clusters of a peak list (lock-free union-find, see k_cluster.hip).
+uint64_t cluster_blocks(uint64_t n);
+hipError_t launch_clusters(hough_ctx *c, const hough_peak *peaks, uint64_t peak_capacity, const uint64_t *poff,
+                           uint32_t n_events, uint32_t *labels, hough_cluster *clusters, uint64_t capacity,
+                           uint64_t *coff, hipStream_t s);
 inline uint32_t peak_rows(const hough_ctx *c)
 {
     return c->tun.peak_rows ? c->tun.peak_rows : 16u;

@@ -22,13 +22,16 @@ EXPORTED = [
     "hough_check_spec", "hough_build_tables", "hough_set_tuning", "hough_get_tuning",
     "hough_set_profiling", "hough_kernel_times", "hough_kernel_times_reset",
     "hough_strerror", "hough_last_error", "hough_device_cus", "hough_gather_events",
-    "hough_vote_count", "hough_peaks_count",
+    "hough_vote_count", "hough_peaks_count", "hough_peak_clusters",
 ]
 
 PEAK_DTYPE = np.dtype([("cell", np.uint32), ("mask", np.uint16), ("popcount", np.uint16)])
 COUNT_PEAK_DTYPE = np.dtype([("cell", np.uint32), ("count", np.uint32)])
 RZ_DTYPE = np.dtype([("peak", np.uint32), ("cot_bin", np.uint16), ("z0_bin", np.uint16),
                      ("count", np.uint32), ("n_members", np.uint32)])
+CLUSTER_DTYPE = np.dtype([("first", np.uint32), ("popcount", np.uint16), ("mask_or", np.uint16),
+                          ("n_peaks", np.uint32), ("sum_dk", np.int32), ("sum_dp", np.int32),
+                          ("sum_dd", np.int32)])
 
 
 class GridSpec(C.Structure):
@@ -94,6 +97,7 @@ def load_library():
         "hough_gather_events": ([P, P, P, P, P, P, u32, P, P, P, P], i32),
         "hough_vote_count": ([P, P, P, P], i32),
         "hough_peaks_count": ([P, P, u32, P, u64, P, P], i32),
+        "hough_peak_clusters": ([P, P, u64, P, u32, P, P, u64, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -330,6 +334,34 @@ class HoughContext:
                self._h, "hough_rz_refine")
         return out, offsets
 
+    def new_clusters(self, capacity):
+        """Cluster records: int64 tensor (8-byte aligned) of 3 words each."""
+        torch = _torch()
+        return torch.empty((max(capacity, 1), 3), dtype=torch.int64, device=f"cuda:{self.device}")
+
+    def new_labels(self, capacity):
+        torch = _torch()
+        return torch.empty(max(capacity, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+
+    def peak_clusters(self, peaks, peak_offsets, n_events, peak_capacity=None, capacity=None, labels=None,
+                      out=None, offsets=None, stream=None):
+        """Plateau clusters of a peak list: (per-peak cluster index within its
+        event, cluster records, event cluster offsets)."""
+        if peak_capacity is None:
+            peak_capacity = peaks.shape[0]
+        if capacity is None:
+            capacity = peak_capacity
+        if labels is None:
+            labels = self.new_labels(peak_capacity)
+        if out is None:
+            out = self.new_clusters(capacity)
+        if offsets is None:
+            offsets = self.new_offsets(n_events)
+        _check(self.lib.hough_peak_clusters(self._h, _ptr(peaks), peak_capacity, _ptr(peak_offsets), n_events,
+                                            _ptr(labels), _ptr(out), capacity, _ptr(offsets), _stream(stream)),
+               self._h, "hough_peak_clusters")
+        return labels, out, offsets
+
     def graph_capture(self, hits, acc, peaks, peak_capacity, peak_offsets, rz=None, rz_capacity=0,
                       rz_offsets=None, stream=None):
         h = hits.struct()
@@ -422,3 +454,23 @@ def rz_numpy(rz, offsets, event=None):
     if event is None:
         return arr
     return arr[int(off[event]):int(off[event + 1])]
+
+
+def clusters_numpy(clusters, offsets, event=None):
+    """Cluster records (all events, or one) as a CLUSTER_DTYPE array."""
+    off = offsets_numpy(offsets)
+    n = int(off[-1])
+    arr = clusters[:min(n, clusters.shape[0])].cpu().numpy().view(CLUSTER_DTYPE).reshape(-1)
+    if event is None:
+        return arr
+    return arr[int(off[event]):int(off[event + 1])]
+
+
+def labels_numpy(labels, peak_offsets, peak_capacity=None, event=None):
+    """Per-peak cluster indices (all stored peaks, or one event's)."""
+    off = offsets_numpy(peak_offsets)
+    cap = labels.shape[0] if peak_capacity is None else peak_capacity
+    arr = labels[:min(int(off[-1]), cap)].cpu().numpy().view(np.uint32)
+    if event is None:
+        return arr
+    return arr[min(int(off[event]), cap):min(int(off[event + 1]), cap)]
