@@ -61,6 +61,8 @@ def _load():
         lib.orc_rz.restype = C.c_uint64
         lib.orc_clusters.argtypes = [P, C.c_uint64, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_clusters.restype = C.c_uint64
+        lib.orc_fit.argtypes = [P, P, P, C.c_uint64, P, P, C.c_uint64, P, P, P, P,
+                                P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -235,6 +237,33 @@ def cluster_centroids(tab, pk, cl):
     k = (f // np_) % nk + cl["sum_dk"] / n
     p = np.mod(f % np_ + cl["sum_dp"] / n, np_)
     return d, k, p
+
+
+FIT_DTYPE = np.dtype([("qpt", np.float64), ("phi0", np.float64), ("qpt_c", np.float64),
+                      ("phi0_c", np.float64), ("rms_mm", np.float64), ("n_hits", np.uint32),
+                      ("status", np.uint32)])
+
+
+def fit(tab, layer, phi, pk, cl):
+    """Track fit of each cluster of one event over the hits that voted into
+    its first peak cell (beam-line grids only), plus its centroid
+    parameters; FIT_DTYPE records in cluster order."""
+    if tab.spec["n_d0"] != 1:
+        raise ValueError("the cluster fit needs a grid without a d0 axis")
+    layer, phi, _ = _hits(layer, phi)
+    n = len(cl)
+    first = np.ascontiguousarray(pk["cell"][cl["first"]], np.uint32)
+    npk = np.ascontiguousarray(cl["n_peaks"], np.uint32)
+    sdk = np.ascontiguousarray(cl["sum_dk"], np.int32)
+    sdp = np.ascontiguousarray(cl["sum_dp"], np.int32)
+    d = [np.zeros(n + 1) for _ in range(5)]
+    u = [np.zeros(n + 1, np.uint32) for _ in range(2)]
+    _load().orc_fit(C.byref(tab.cs), _p(tab.O), _p(tab.V), len(layer), _p(layer), _p(phi), n,
+                    _p(first), _p(npk), _p(sdk), _p(sdp), *[_p(x) for x in d], *[_p(x) for x in u])
+    out = np.zeros(n, FIT_DTYPE)
+    for name, x in zip(FIT_DTYPE.names, d + u):
+        out[name] = x[:n]
+    return out
 
 
 def run_event(tab, layer, phi, z=None, with_rz=None):

@@ -438,3 +438,94 @@ uint64_t orc_clusters(const orc_spec *g, uint64_t n, const uint32_t *cell, const
     free(at); free(queue);
     return n_cl;
 }
+
+/* ---- candidate confirmation: track fit of a cluster --------------------
+ *
+ * For a beam-line grid (n_d0 == 1, d0 = 0) a hit at radius r and azimuth
+ * phi lies on the track (q/pT, phi0) when r sin(phi - phi0) + rho r^2 / 2 = 0
+ * (the track model above with d0 = 0), i.e. with x = r cos phi, y = r sin phi:
+ *     y cos phi0 - x sin phi0 + rho r^2 / 2 = 0.
+ * In a frame rotated by a reference azimuth phi_ref close to the track
+ * (x', y' the rotated coordinates, phi0' = phi0 - phi_ref, |phi0'| < pi/2)
+ * dividing by cos phi0' makes this linear in t = tan phi0' and
+ * alpha = rho / (2 cos phi0'):   y' = t x' - alpha r^2.
+ * The fit is the least-squares solution over the members, from the normal
+ * equations  [Sxx  -Sxw; -Sxw  Sww] [t; alpha] = [Sxy; -Syw]  (w = r^2),
+ * by Cramer's rule; then phi0 = phi_ref + atan t, rho = 2 alpha cos phi0',
+ * q/pT = rho / (0.299792458e-3 B).  The residual of a member is
+ * (y' - t x' + alpha w) cos phi0' (mm, its distance from the curve to first
+ * order); rms over the members.
+ *
+ * Members: the hits that voted into the cluster's first peak cell (k_f, p_f)
+ * -- layer l < n_layers, row valid, ((phi - O[l][k_f]) >> shift) == p_f.
+ * phi_ref: the centre of that cell's phi0 bin.  status = 1 when there are at
+ * least 3 members and det = Sxx Sww - Sxw^2 > 1e-12 Sxx Sww, else 0 with
+ * zero fit outputs.  The centroid parameters are the bin-centre formulas
+ * evaluated at the centroid: q/pT_c = qpt_lo + (k_c + 1/2) (qpt_hi - qpt_lo)
+ * / n_qpt, phi0_c = 2 pi ((p_c + 1/2) / n_phi mod 1). */
+void orc_fit(const orc_spec *g, const uint32_t *O, const uint8_t *V,
+             uint64_t n_hits, const uint8_t *layer, const uint32_t *phi,
+             uint64_t n_clusters, const uint32_t *first_cell, const uint32_t *n_peaks,
+             const int32_t *sum_dk, const int32_t *sum_dp,
+             double *qpt, double *phi0, double *qpt_c, double *phi0_c, double *rms,
+             uint32_t *n_fit, uint32_t *status)
+{
+    const double two_pi = 2.0 * M_PI;
+    const double turn_rad = two_pi / 4294967296.0;
+    uint32_t s = 32 - log2u(g->n_phi);
+    for (uint64_t c = 0; c < n_clusters; c++) {
+        uint32_t k = (first_cell[c] / g->n_phi) % g->n_qpt;
+        uint32_t p = first_cell[c] % g->n_phi;
+        double n = (double)n_peaks[c];
+        double kc = (double)k + (double)sum_dk[c] / n;
+        double pc = (double)p + (double)sum_dp[c] / n;
+        qpt_c[c] = g->qpt_lo + (kc + 0.5) * ((g->qpt_hi - g->qpt_lo) / g->n_qpt);
+        double f = fmod((pc + 0.5) / (double)g->n_phi, 1.0);
+        if (f < 0) f += 1.0;
+        phi0_c[c] = two_pi * f;
+
+        uint32_t ref = (p << s) + (1u << (s - 1));
+        double sxx = 0, sxw = 0, sww = 0, sxy = 0, syw = 0;
+        uint32_t m = 0;
+        for (int pass = 0; pass < 2; pass++) {
+            double t = 0, alpha = 0, cosp = 0, ss = 0;
+            if (pass == 1) {
+                double det = sxx * sww - sxw * sxw;
+                if (m < 3 || !(det > 1e-12 * sxx * sww)) break;
+                t = (sxy * sww - sxw * syw) / det;
+                alpha = (sxw * sxy - sxx * syw) / det;
+                cosp = 1.0 / sqrt(1.0 + t * t);
+            }
+            for (uint64_t h = 0; h < n_hits; h++) {
+                uint32_t l = layer[h];
+                if (l >= g->n_layers) continue;
+                size_t ti = (size_t)l * g->n_qpt + k;
+                if (!V[ti] || ((uint32_t)(phi[h] - O[ti]) >> s) != p) continue;
+                double ang = (double)(int32_t)(phi[h] - ref) * turn_rad;
+                double r = g->layer_r_mm[l];
+                double x = r * cos(ang), y = r * sin(ang), w = r * r;
+                if (pass == 0) {
+                    sxx += x * x; sxw += x * w; sww += w * w; sxy += x * y; syw += y * w;
+                    m++;
+                } else {
+                    double res = (y - t * x + alpha * w) * cosp;
+                    ss += res * res;
+                }
+            }
+            if (pass == 1) {
+                double ph = (double)ref * turn_rad + atan(t);
+                ph = fmod(ph, two_pi);
+                if (ph < 0) ph += two_pi;
+                phi0[c] = ph;
+                qpt[c] = 2.0 * alpha * cosp / (0.299792458e-3 * g->b_tesla);
+                rms[c] = sqrt(ss / m);
+                status[c] = 1;
+            }
+        }
+        n_fit[c] = m;
+        if (m < 3 || !(sxx * sww - sxw * sxw > 1e-12 * sxx * sww)) {
+            qpt[c] = phi0[c] = rms[c] = 0.0;
+            status[c] = 0;
+        }
+    }
+}

@@ -693,3 +693,100 @@ def test_clusters_of_real_peaks_are_equal_valued_and_separated():
     adj = (dk <= 1) & (np.minimum(dp, 64 - dp) <= 1)
     same = lab[:, None] == lab[None, :]
     assert not np.any(adj & ~same)
+
+
+# --------------------------------------------------------------------------
+# Candidate confirmation: track fit over a cluster's first-cell members
+# --------------------------------------------------------------------------
+
+def _clusters_of(tab, layer, phi):
+    pk = oracle.peaks(tab, oracle.vote_mask(tab, layer, phi))
+    lab, cl = oracle.clusters(tab, pk)
+    return pk, cl
+
+
+@pytest.mark.parametrize("name,qpt,phi0", [
+    ("c2_single_1ktrk_rz", 0.3131, 1.234), ("c2_single_1ktrk_rz", -0.8765, 4.5678),
+    ("c2_single_1ktrk_rz", 0.0217, 0.0004), ("c2_single_1ktrk_rz", -0.5, 2 * math.pi - 0.0007),
+    ("c1_single_100trk", 0.61, 3.0), ("c1_single_100trk", -0.05, 5.9)])
+def test_fit_recovers_generator_track(name, qpt, phi0):
+    # noiseless hits from the generator's own helix construction, at track
+    # parameters off the bin centres: the fit lands on the true parameters
+    # (to the uint32 azimuth quantisation), closer than the cluster centroid
+    spec = synth.grid_spec(name)
+    tab = oracle.Tables(spec)
+    layer, phi, _ = synth.track_hits(qpt, phi0)
+    pk, cl = _clusters_of(tab, layer, phi)
+    f = oracle.fit(tab, layer, phi, pk, cl)
+    good = f[f["status"] == 1]
+    # side plateaus of a lower popcount can form their own clusters; every
+    # member is still a hit of this track
+    assert np.any((good["n_hits"] == 10) & (cl["popcount"][f["status"] == 1] == 10))
+    assert np.all(np.abs(good["qpt"] - qpt) < 2e-6)
+    dphi = np.angle(np.exp(1j * (good["phi0"] - phi0)))
+    assert np.all(np.abs(dphi) < 1e-7)
+    assert np.all(good["rms_mm"] < 1e-5)
+    assert np.all((good["phi0"] >= 0) & (good["phi0"] < 2 * math.pi))
+    dc = np.abs(good["qpt_c"] - qpt)
+    assert np.all(np.abs(good["qpt"] - qpt) < dc + 1e-12)
+
+
+def test_fit_matches_lstsq_on_noisy_members():
+    # with noise hits among the members the fit is the least-squares
+    # solution of the linear system y' = t x' - alpha r^2 (numpy lstsq)
+    spec = synth.grid_spec("c1_single_100trk")
+    tab = oracle.Tables(spec)
+    rng = np.random.default_rng(21)
+    layer, phi, _ = synth.track_hits(rng.uniform(-0.9, 0.9, 40), rng.uniform(0, 2 * math.pi, 40),
+                                     rng=rng)
+    nl, nphi, _ = random_hits(rng, 3000)
+    layer, phi = np.concatenate([layer, nl]), np.concatenate([phi, nphi])
+    pk, cl = _clusters_of(tab, layer, phi)
+    f = oracle.fit(tab, layer, phi, pk, cl)
+    s = 32 - 8
+    R = np.asarray(spec["layer_r_mm"][:spec["n_layers"]])
+    checked = 0
+    for c in np.flatnonzero(f["status"] == 1)[:300]:
+        cell = int(pk["cell"][cl["first"][c]])
+        k, p = cell // 256, cell % 256
+        mem = [h for h in range(len(layer)) if tab.V[layer[h], 0, k]
+               and ((int(phi[h]) - int(tab.O[layer[h], 0, k])) % (1 << 32)) >> s == p]
+        assert len(mem) == f["n_hits"][c]
+        ref = (p << s) + (1 << (s - 1))
+        ang = ((phi[mem].astype(np.int64) - ref + (1 << 31)) % (1 << 32) - (1 << 31)) * (2 * math.pi / 2 ** 32)
+        r = R[layer[mem]]
+        x, y = r * np.cos(ang), r * np.sin(ang)
+        sol, *_ = np.linalg.lstsq(np.stack([x, -r * r], 1), y, rcond=None)
+        t, alpha = sol
+        cosp = 1 / math.sqrt(1 + t * t)
+        assert f["phi0"][c] == pytest.approx((ref * 2 * math.pi / 2 ** 32 + math.atan(t)) % (2 * math.pi),
+                                             abs=1e-9)
+        assert f["qpt"][c] == pytest.approx(2 * alpha * cosp / (0.299792458e-3 * spec["b_tesla"]),
+                                            rel=1e-7, abs=1e-9)
+        res = (y - t * x + alpha * r * r) * cosp
+        assert f["rms_mm"][c] == pytest.approx(math.sqrt(np.mean(res ** 2)), rel=1e-6, abs=1e-9)
+        checked += 1
+    assert checked >= 20
+
+
+def test_fit_centroid_and_degenerate_clusters():
+    spec = synth.grid_spec("c2_single_1ktrk_rz")
+    tab = oracle.Tables(spec)
+    K, N = spec["n_qpt"], spec["n_phi"]
+    kap = centres(spec["qpt_lo"], spec["qpt_hi"], K)
+    k, p = 700, 3
+    layer, phi, _ = synth.track_hits(kap[k], (p + 0.5) / N * 2 * math.pi)
+    pk, cl = _clusters_of(tab, layer, phi)
+    f = oracle.fit(tab, layer, phi, pk, cl)
+    assert len(f) == 1
+    assert f["qpt_c"][0] == pytest.approx(kap[k], abs=1e-12)
+    assert f["phi0_c"][0] == pytest.approx((p + 0.5) / N * 2 * math.pi, abs=1e-12)
+    # a cluster whose first cell holds fewer than three hits is not fitted
+    fake = np.zeros(2, oracle.PEAK_DTYPE)
+    fake["cell"] = [5 * N + 100, 9 * N + 7]
+    lab, fcl = oracle.clusters(tab, fake)
+    two = np.zeros(2, np.uint8), np.array([0, 1 << 20], np.uint32)
+    g = oracle.fit(tab, two[0], two[1], fake, fcl)
+    assert g["status"].tolist() == [0, 0]
+    assert np.all(g["qpt"] == 0) and np.all(g["rms_mm"] == 0)
+    assert g["qpt_c"][1] == pytest.approx(kap[9], abs=1e-12)
