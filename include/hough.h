@@ -145,6 +145,17 @@ typedef struct {
     int32_t  sum_dd;                /* sum over members of d - d_f */
 } hough_cluster;
 
+/* Track fit of one plateau cluster (hough_cluster_fit).  48 bytes. */
+typedef struct {
+    double   qpt;                   /* fitted q/pT, 1/GeV (0 when status == 0) */
+    double   phi0;                  /* fitted phi0, radians in [0, 2 pi) (0 when status == 0) */
+    double   qpt_c;                 /* q/pT at the cluster centroid (bin-centre formula) */
+    double   phi0_c;                /* phi0 at the cluster centroid, radians in [0, 2 pi) */
+    double   rms_mm;                /* rms residual of the members, mm (0 when status == 0) */
+    uint32_t n_hits;                /* members: hits that voted into the first peak's cell */
+    uint32_t status;                /* 1 = fitted; 0 = fewer than 3 members or singular */
+} hough_fit;
+
 /* Autotuning knobs of the kernels (all 0 = library default). */
 typedef struct {
     uint32_t vote_rows;             /* accumulator rows per LDS tile */
@@ -238,6 +249,28 @@ int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_c
                         const uint64_t *event_peak_offsets, uint32_t n_events, uint32_t *peak_cluster,
                         hough_cluster *clusters, uint64_t capacity, uint64_t *event_cluster_offsets,
                         void *stream);
+
+/* Candidate confirmation, track fit (grids without a d0 axis; HOUGH_EINVAL
+ * when n_d0 > 1).  On such a grid a hit (r, phi) lies on the track (q/pT,
+ * phi0) when y cos phi0 - x sin phi0 + rho r^2 / 2 = 0, x = r cos phi,
+ * y = r sin phi, rho = 0.299792458e-3 B q/pT (the track model of the vote's
+ * offset tables with d0 = 0).  For every cluster c < min(coff[n_events],
+ * capacity): members are the hits of its event that voted into its first
+ * peak's cell (k, p); in the frame rotated by the centre azimuth of phi0 bin
+ * p the model reads y' = t x' - alpha r^2 with t = tan(phi0 - phi_ref),
+ * alpha = rho / (2 cos(phi0 - phi_ref)), and (t, alpha) is the least-squares
+ * solution over the members (normal equations, Cramer's rule; status 1 when
+ * there are >= 3 members and det > 1e-12 Sxx Sww).  rms_mm is the rms of
+ * (y' - t x' + alpha r^2) cos(phi0 - phi_ref) over the members.  qpt_c and
+ * phi0_c evaluate the bin-centre formulas at the centroid.  Records go to
+ * out[c] (device, `capacity` records, 8-byte aligned).  hits are the hits
+ * the peaks were found from (same n_events); peaks/event_peak_offsets are
+ * hough_peaks' outputs, clusters/event_cluster_offsets hough_peak_clusters'.
+ * fp64 arithmetic; members are summed in a fixed order on the device, so
+ * results agree with a serial evaluation to rounding. */
+int hough_cluster_fit(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks, uint64_t peak_capacity,
+                      const uint64_t *event_peak_offsets, const hough_cluster *clusters, uint64_t capacity,
+                      const uint64_t *event_cluster_offsets, hough_fit *out, void *stream);
 
 /* Confirmation: rz refinement of the candidates of each event (needs
  * n_z0 > 0).  Candidates of event e are its peaks in list order, or, when

@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["api.hip", "k_util.hip", "k_bucket.hip", "k_vote.hip", "k_vote_gap.hip", "k_vote_direct.hip", "k_peaks.hip", "k_rz.hip",
-               "k_cluster.hip"]
+               "k_cluster.hip", "k_fit.hip"]
 CXX_SOURCES = ["tables.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

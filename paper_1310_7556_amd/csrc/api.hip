@@ -333,6 +333,23 @@ int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_c
     return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peak_clusters");
 }
 
+int hough_cluster_fit(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks, uint64_t peak_capacity,
+                      const uint64_t *event_peak_offsets, const hough_cluster *clusters, uint64_t capacity,
+                      const uint64_t *event_cluster_offsets, hough_fit *out, void *stream)
+{
+    if (!ctx || ctx->spec.n_d0 != 1 || !hits_ok(ctx, hits, false) || !event_peak_offsets ||
+        !event_cluster_offsets || (peak_capacity && !peaks) || (capacity && (!clusters || !out)))
+        return HOUGH_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(peaks) & 7) || (reinterpret_cast<uintptr_t>(clusters) & 7) ||
+        (reinterpret_cast<uintptr_t>(out) & 7))
+        return HOUGH_EINVAL;
+    if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = launch_fit(ctx, hits, peaks, peak_capacity, event_peak_offsets, clusters, capacity,
+                                    event_cluster_offsets, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_cluster_fit");
+}
+
 int hough_rz_refine(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks,
                     uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
                     uint64_t capacity, uint64_t *event_rz_offsets, void *stream)

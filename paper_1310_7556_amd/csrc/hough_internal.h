@@ -144,6 +144,9 @@ uint64_t cluster_blocks(uint64_t n);
 hipError_t launch_clusters(hough_ctx *c, const hough_peak *peaks, uint64_t peak_capacity, const uint64_t *poff,
                            uint32_t n_events, uint32_t *labels, hough_cluster *clusters, uint64_t capacity,
                            uint64_t *coff, hipStream_t s);
+hipError_t launch_fit(hough_ctx *c, const hough_hits *h, const hough_peak *peaks, uint64_t peak_capacity,
+                      const uint64_t *poff, const hough_cluster *clusters, uint64_t capacity, const uint64_t *coff,
+                      hough_fit *out, hipStream_t s);
 inline uint32_t peak_rows(const hough_ctx *c)
 {
     return c->tun.peak_rows ? c->tun.peak_rows : 16u;

@@ -1,0 +1,194 @@
+// Candidate confirmation, second part: a track fit per plateau cluster.
+//
+// For a beam-line grid (no d0 axis) a hit (r, phi) lies on the track
+// (q/pT, phi0) when y cos phi0 - x sin phi0 + rho r^2 / 2 = 0 with
+// x = r cos phi, y = r sin phi and rho = 0.299792458e-3 B q/pT (the track
+// model of the offset tables with d0 = 0).  Rotated by a reference azimuth
+// phi_ref close to the track and divided by cos(phi0 - phi_ref) this is
+// linear: y' = t x' - alpha r^2 with t = tan(phi0 - phi_ref) and
+// alpha = rho / (2 cos(phi0 - phi_ref)).  Least squares over the members
+// gives the 2x2 normal equations, solved by Cramer's rule.
+//
+// Members are the hits that voted into the cluster's first peak cell; the
+// reference azimuth is the centre of that cell's phi0 bin.  One wave per
+// cluster: pass 1 sums x'^2, x' r^2, r^4, x' y', y' r^2 over the members of
+// the event's layer-grouped hits (lanes over hits, one layer at a time, so
+// the row offset is wave-uniform), pass 2 the squared residuals of the
+// solution; fp64 throughout, wave sums by a fixed butterfly.
+#include "hough_internal.h"
+
+namespace hough {
+namespace {
+
+struct FitParams {
+    const uint32_t *phi_a;        // layer-grouped azimuths of all events
+    const uint32_t *layer_off;    // [E][L + 1] relative to the event start
+    const uint64_t *hoff;         // [E + 1] hit offsets
+    uint64_t n_hits;
+    const uint2 *pk;              // peak records
+    uint64_t peak_cap;
+    const uint64_t *poff;         // [E + 1]
+    const hough_cluster *cl;
+    uint64_t cl_cap;
+    const uint64_t *coff;         // [E + 1]
+    uint32_t E;
+    hough_fit *out;
+    const uint32_t *O;            // [L][n_qpt]
+    const uint8_t *V;
+    double r_mm[kMaxLayers];
+    uint32_t n_layers, n_qpt, n_phi, log2_phi, shift;
+    double qpt_lo, qpt_w;         // bin width (qpt_hi - qpt_lo) / n_qpt
+    double inv_curv;              // 1 / (0.299792458e-3 B)
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v)
+{
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_fit(FitParams P)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave0 = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t waves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    const uint64_t n_cl = min(P.coff[P.E], P.cl_cap);
+    const double two_pi = 6.283185307179586476925286766559;
+    const double turn_rad = two_pi / 4294967296.0;
+    const uint32_t pmask = P.n_phi - 1, L = P.n_layers;
+    for (uint64_t c = wave0; c < n_cl; c += waves) {
+        // event of cluster c: largest e with start(e) <= c
+        uint32_t lo = 0, hi = P.E;
+        while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (min(P.coff[m], n_cl) <= c) lo = m;
+            else hi = m;
+        }
+        const uint32_t e = lo;
+        const hough_cluster rec = P.cl[c];
+        const uint64_t pe0 = min(P.poff[e], P.peak_cap), pe1 = min(max(P.poff[e + 1], P.poff[e]), P.peak_cap);
+        const uint64_t gi = pe0 + rec.first;
+        hough_fit f{};
+        if (gi < pe1 && rec.n_peaks > 0) {
+            const uint32_t cell = P.pk[gi].x;
+            const uint32_t p = cell & pmask, k = (cell >> P.log2_phi) % P.n_qpt;
+            const double n = double(rec.n_peaks);
+            const double kc = double(k) + double(rec.sum_dk) / n;
+            const double pc = double(p) + double(rec.sum_dp) / n;
+            f.qpt_c = P.qpt_lo + (kc + 0.5) * P.qpt_w;
+            double fr = fmod((pc + 0.5) / double(P.n_phi), 1.0);
+            if (fr < 0) fr += 1.0;
+            f.phi0_c = two_pi * fr;
+
+            const uint64_t eb = min(P.hoff[e], P.n_hits);
+            const uint32_t *lof = P.layer_off + size_t(e) * (L + 1);
+            const uint32_t ref = (p << P.shift) + (1u << (P.shift - 1));
+            double sxx = 0, sxw = 0, sww = 0, sxy = 0, syw = 0;
+            uint32_t m = 0;
+            for (uint32_t l = 0; l < L; ++l) {
+                const size_t ti = size_t(l) * P.n_qpt + k;
+                if (!P.V[ti]) continue;
+                const uint32_t o = P.O[ti];
+                const double r = P.r_mm[l], w = r * r;
+                for (uint32_t j = lof[l] + lane; j < lof[l + 1]; j += 64) {
+                    const uint32_t ph = P.phi_a[eb + j];
+                    if (((ph - o) >> P.shift) != p) continue;
+                    double sa, ca;
+                    sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
+                    const double x = r * ca, y = r * sa;
+                    sxx += x * x;
+                    sxw += x * w;
+                    sww += w * w;
+                    sxy += x * y;
+                    syw += y * w;
+                    ++m;
+                }
+            }
+            sxx = wave_sum(sxx);
+            sxw = wave_sum(sxw);
+            sww = wave_sum(sww);
+            sxy = wave_sum(sxy);
+            syw = wave_sum(syw);
+            m = wave_sum_u(m);
+            f.n_hits = m;
+            const double det = sxx * sww - sxw * sxw;
+            if (m >= 3 && det > 1e-12 * sxx * sww) {
+                const double t = (sxy * sww - sxw * syw) / det;
+                const double alpha = (sxw * sxy - sxx * syw) / det;
+                const double cosp = 1.0 / sqrt(1.0 + t * t);
+                double ss = 0;
+                for (uint32_t l = 0; l < L; ++l) {
+                    const size_t ti = size_t(l) * P.n_qpt + k;
+                    if (!P.V[ti]) continue;
+                    const uint32_t o = P.O[ti];
+                    const double r = P.r_mm[l], w = r * r;
+                    for (uint32_t j = lof[l] + lane; j < lof[l + 1]; j += 64) {
+                        const uint32_t ph = P.phi_a[eb + j];
+                        if (((ph - o) >> P.shift) != p) continue;
+                        double sa, ca;
+                        sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
+                        const double res = (r * sa - t * (r * ca) + alpha * w) * cosp;
+                        ss += res * res;
+                    }
+                }
+                ss = wave_sum(ss);
+                double ph0 = fmod(double(ref) * turn_rad + atan(t), two_pi);
+                if (ph0 < 0) ph0 += two_pi;
+                f.phi0 = ph0;
+                f.qpt = 2.0 * alpha * cosp * P.inv_curv;
+                f.rms_mm = sqrt(ss / m);
+                f.status = 1;
+            }
+        }
+        if (lane == 0) P.out[c] = f;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fit(hough_ctx *c, const hough_hits *h, const hough_peak *peaks, uint64_t peak_capacity,
+                      const uint64_t *poff, const hough_cluster *clusters, uint64_t capacity, const uint64_t *coff,
+                      hough_fit *out, hipStream_t s)
+{
+    if (h->n_events == 0 || capacity == 0) return hipSuccess;
+    hipError_t err = launch_bucket_layers(c, h, false, s);
+    if (err != hipSuccess) return err;
+    FitParams P{};
+    P.phi_a = c->d_phi_a;
+    P.layer_off = c->d_layer_off;
+    P.hoff = h->event_offsets;
+    P.n_hits = h->n_hits;
+    P.pk = reinterpret_cast<const uint2 *>(peaks);
+    P.peak_cap = peak_capacity;
+    P.poff = poff;
+    P.cl = clusters;
+    P.cl_cap = capacity;
+    P.coff = coff;
+    P.E = h->n_events;
+    P.out = out;
+    P.O = c->d_O;
+    P.V = c->d_V;
+    for (uint32_t l = 0; l < c->spec.n_layers && l < kMaxLayers; ++l) P.r_mm[l] = c->spec.layer_r_mm[l];
+    P.n_layers = c->spec.n_layers;
+    P.n_qpt = c->spec.n_qpt;
+    P.n_phi = c->spec.n_phi;
+    P.log2_phi = c->log2_phi;
+    P.shift = c->shift;
+    P.qpt_lo = c->spec.qpt_lo;
+    P.qpt_w = (c->spec.qpt_hi - c->spec.qpt_lo) / c->spec.n_qpt;
+    P.inv_curv = 1.0 / (0.299792458e-3 * c->spec.b_tesla);
+    const uint64_t blocks = std::min<uint64_t>((capacity + 3) / 4, uint64_t(c->n_cu) * 8);
+    KernelTimer t;
+    prof_begin(c, "cluster_fit", s, &t);
+    hipLaunchKernelGGL(k_fit, dim3(uint32_t(std::max<uint64_t>(blocks, 1))), dim3(256), 0, s, P);
+    prof_end(c, s, &t);
+    return hipGetLastError();
+}
+
+}  // namespace hough

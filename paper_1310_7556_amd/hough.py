@@ -23,6 +23,7 @@ EXPORTED = [
     "hough_set_profiling", "hough_kernel_times", "hough_kernel_times_reset",
     "hough_strerror", "hough_last_error", "hough_device_cus", "hough_gather_events",
     "hough_vote_count", "hough_peaks_count", "hough_peak_clusters",
+    "hough_cluster_fit",
 ]
 
 PEAK_DTYPE = np.dtype([("cell", np.uint32), ("mask", np.uint16), ("popcount", np.uint16)])
@@ -32,6 +33,9 @@ RZ_DTYPE = np.dtype([("peak", np.uint32), ("cot_bin", np.uint16), ("z0_bin", np.
 CLUSTER_DTYPE = np.dtype([("first", np.uint32), ("popcount", np.uint16), ("mask_or", np.uint16),
                           ("n_peaks", np.uint32), ("sum_dk", np.int32), ("sum_dp", np.int32),
                           ("sum_dd", np.int32)])
+FIT_DTYPE = np.dtype([("qpt", np.float64), ("phi0", np.float64), ("qpt_c", np.float64),
+                      ("phi0_c", np.float64), ("rms_mm", np.float64), ("n_hits", np.uint32),
+                      ("status", np.uint32)])
 
 
 class GridSpec(C.Structure):
@@ -98,6 +102,7 @@ def load_library():
         "hough_vote_count": ([P, P, P, P], i32),
         "hough_peaks_count": ([P, P, u32, P, u64, P, P], i32),
         "hough_peak_clusters": ([P, P, u64, P, u32, P, P, u64, P, P], i32),
+        "hough_cluster_fit": ([P, P, P, u64, P, P, u64, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -362,6 +367,26 @@ class HoughContext:
                self._h, "hough_peak_clusters")
         return labels, out, offsets
 
+    def new_fits(self, capacity):
+        """Fit records: float64 tensor of 6 words each."""
+        torch = _torch()
+        return torch.empty((max(capacity, 1), 6), dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def cluster_fit(self, hits, peaks, peak_offsets, clusters, cluster_offsets, peak_capacity=None,
+                    capacity=None, out=None, stream=None):
+        """Track fit of every stored cluster (grids without a d0 axis)."""
+        if peak_capacity is None:
+            peak_capacity = peaks.shape[0]
+        if capacity is None:
+            capacity = clusters.shape[0]
+        if out is None:
+            out = self.new_fits(capacity)
+        h = hits.struct()
+        _check(self.lib.hough_cluster_fit(self._h, C.byref(h), _ptr(peaks), peak_capacity, _ptr(peak_offsets),
+                                          _ptr(clusters), capacity, _ptr(cluster_offsets), _ptr(out),
+                                          _stream(stream)), self._h, "hough_cluster_fit")
+        return out
+
     def graph_capture(self, hits, acc, peaks, peak_capacity, peak_offsets, rz=None, rz_capacity=0,
                       rz_offsets=None, stream=None):
         h = hits.struct()
@@ -474,3 +499,13 @@ def labels_numpy(labels, peak_offsets, peak_capacity=None, event=None):
     if event is None:
         return arr
     return arr[min(int(off[event]), cap):min(int(off[event + 1]), cap)]
+
+
+def fits_numpy(fits, cluster_offsets, event=None):
+    """Fit records (all stored clusters, or one event's) as a FIT_DTYPE array."""
+    off = offsets_numpy(cluster_offsets)
+    n = int(off[-1])
+    arr = fits[:min(n, fits.shape[0])].cpu().numpy().view(FIT_DTYPE).reshape(-1)
+    if event is None:
+        return arr
+    return arr[int(off[event]):int(off[event + 1])]

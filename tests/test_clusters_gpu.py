@@ -228,3 +228,98 @@ def test_cluster_limits_and_bad_arguments(H):
     assert H.offsets_numpy(coff).tolist() == [0, 0, 0]
     with pytest.raises(H.HoughError):
         H.HoughContext(spec, max_events=1, max_hits=16, max_peaks=1 << 32)
+
+
+# --------------------------------------------------------------------------
+# track fit of each cluster
+# --------------------------------------------------------------------------
+
+# fp64 throughout; the device sums members in another order and uses its own
+# sin/cos (within 2 ulp).  With at most a few hundred members and normal
+# equations whose condition number stays below ~1e5 on these workloads, the
+# differences are below 1e-10 in q/pT (1/GeV), phi0 (rad) and rms (mm); the
+# bar leaves a factor 100 of margin.
+FIT_TOL = 1e-8
+WORST = {}
+
+
+def check_fit(H, got, want, what=""):
+    np.testing.assert_array_equal(got["n_hits"], want["n_hits"], err_msg=f"n_hits {what}")
+    np.testing.assert_array_equal(got["status"], want["status"], err_msg=f"status {what}")
+    for f in ("qpt", "phi0", "qpt_c", "phi0_c", "rms_mm"):
+        d = np.abs(got[f] - want[f])
+        if f.startswith("phi0"):
+            d = np.minimum(d, 2 * np.pi - d)            # the same angle across the wrap
+        scale = np.maximum(1.0, np.abs(want[f]))
+        assert np.all(d <= FIT_TOL * scale), (f, what, float(d.max()))
+        WORST[f] = max(WORST.get(f, 0.0), float(d.max()) if len(d) else 0.0)
+
+
+def run_fit(H, name, batch, events=None, cl_cap=None):
+    import torch
+    spec = synth.grid_spec(name)
+    tab = oracle.Tables(spec)
+    E = batch.n_events
+    cap = E * tab.cells
+    ctx = H.HoughContext(spec, max_events=E, max_hits=max(batch.n_hits, 1), max_peaks=cap)
+    hits = H.DeviceHits.from_batch(batch)
+    pk, poff = ctx.peaks(ctx.vote(hits), E, capacity=cap)
+    cl_cap = min(cap, 1 << 26) if cl_cap is None else cl_cap
+    labels, cl, coff = ctx.peak_clusters(pk, poff, E, capacity=cl_cap)
+    fits = ctx.cluster_fit(hits, pk, poff, cl, coff, peak_capacity=cap, capacity=cl_cap)
+    torch.cuda.synchronize()
+    gco = H.offsets_numpy(coff)
+    for e in (range(E) if events is None else events):
+        ev = batch.event(e)
+        opk = oracle.peaks(tab, oracle.vote_mask(tab, ev.layer, ev.phi))
+        _, ocl = oracle.clusters(tab, opk)
+        want = oracle.fit(tab, ev.layer, ev.phi, opk, ocl)
+        lo, hi = min(int(gco[e]), cl_cap), min(int(gco[e + 1]), cl_cap)
+        got = fits[lo:hi].cpu().numpy().view(H.FIT_DTYPE).reshape(-1)
+        check_fit(H, got, want[:hi - lo], what=f"event {e}")
+    return fits, coff
+
+
+def test_fit_c1_full(H):
+    run_fit(H, "c1_single_100trk", synth.gen_config("c1_single_100trk"))
+
+
+def test_fit_c2_full(H):
+    name = "c2_single_1ktrk_rz"
+    fits, coff = run_fit(H, name, synth.gen_config(name))
+    f = H.fits_numpy(fits, coff)
+    assert np.count_nonzero(f["status"]) > len(f) // 2
+
+
+def test_fit_c4_sampled_events_and_cluster_capacity(H):
+    name = "c4_batch_4096"
+    batch = synth.gen_batch(name, 64)
+    run_fit(H, name, batch, events=[0, 1, 31, 63])
+    # only the stored clusters are fitted: events past the capacity get none
+    run_fit(H, name, batch, events=[0, 1], cl_cap=1000)
+
+
+def test_fit_generator_tracks_recover_truth(H):
+    # noiseless tracks off the bin centres: the device fit lands on the
+    # generator's parameters, as the oracle's does
+    name = "c2_single_1ktrk_rz"
+    spec = synth.grid_spec(name)
+    truth = [(0.3131, 1.234), (-0.8765, 4.5678), (0.0217, 0.0004), (-0.5, 2 * np.pi - 0.0007)]
+    from synth.events import concat_events
+    batch = concat_events([synth.track_hits(q, p) for q, p in truth])
+    fits, coff = run_fit(H, name, batch)
+    for e, (q, p) in enumerate(truth):
+        f = H.fits_numpy(fits, coff, e)
+        good = f[f["status"] == 1]
+        assert len(good) and np.all(np.abs(good["qpt"] - q) < 2e-6)
+        assert np.all(np.abs(np.angle(np.exp(1j * (good["phi0"] - p)))) < 1e-7)
+
+
+def test_fit_rejects_d0_grid_and_reports_worst_difference(H):
+    spec = synth.grid_spec("c3_pileup_displaced_3d")
+    ctx = H.HoughContext(spec, max_events=1, max_hits=16, max_peaks=16)
+    hits = H.DeviceHits(np.zeros(1, np.uint8), np.zeros(1, np.uint32), None, np.array([0, 1], np.uint64))
+    pk, off = ctx.new_peaks(16), ctx.new_offsets(1)
+    with pytest.raises(H.HoughError):
+        ctx.cluster_fit(hits, pk, off, ctx.new_clusters(4), off, peak_capacity=16, capacity=4)
+    print("largest fit differences from the oracle:", WORST)
