@@ -407,6 +407,60 @@ def bench_count_form(H, torch, reps=5):
                 "0.4 mm hits, no noise", sweep=sweep)
 
 
+def bench_confirmation(H, torch, reps=5, c4_events=512):
+    """Candidate confirmation after the peak search: plateau clusters of the
+    peak list and the track fit of every cluster, on the single-event c2
+    workload and on the first c4_events events of the c4 batch.  Kernel times
+    from the library's HIP-event timers, averaged over reps calls; the
+    oracle's clusters + fit of the c2 event timed beside it."""
+    import synth
+    out = {}
+    for name, n_ev in (("c2_single_1ktrk_rz", None), ("c4_batch_4096", c4_events)):
+        spec = synth.grid_spec(name)
+        batch = synth.gen_config(name) if n_ev is None else synth.gen_batch(name, n_ev)
+        E = batch.n_events
+        cap = E * spec["n_qpt"] * spec["n_phi"] * spec["n_d0"]
+        ctx = H.HoughContext(spec, max_events=E, max_hits=batch.n_hits, max_peaks=cap)
+        hits = H.DeviceHits.from_batch(batch)
+        pk, poff = ctx.peaks(ctx.vote(hits), E, capacity=cap)
+        ccap = min(cap, 1 << 25)
+        lab, cl, coff = ctx.peak_clusters(pk, poff, E, capacity=ccap)
+        fits = ctx.cluster_fit(hits, pk, poff, cl, coff, peak_capacity=cap, capacity=ccap)
+        torch.cuda.synchronize()
+        ctx.kernel_times_reset()
+        ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.peak_clusters(pk, poff, E, capacity=ccap, labels=lab, out=cl, offsets=coff)
+            ctx.cluster_fit(hits, pk, poff, cl, coff, peak_capacity=cap, capacity=ccap, out=fits)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        ctx.set_profiling(False)
+        kt = {k: round(v[1] / v[0], 4) for k, v in ctx.kernel_times().items() if v[0]}
+        n_pk = int(H.offsets_numpy(poff)[-1])
+        n_cl = int(H.offsets_numpy(coff)[-1])
+        f = H.fits_numpy(fits, coff)
+        r = dict(events=E, peaks=n_pk, clusters=n_cl, fitted=int(np.count_nonzero(f["status"])),
+                 mean_members=round(float(f["n_hits"].mean()), 2) if len(f) else 0.0,
+                 ms_per_call=round(wall * 1e3, 4), kernel_ms=kt,
+                 clusters_ms=round(sum(v for k, v in kt.items() if k.startswith("cluster_") and
+                                       k != "cluster_fit") + kt.get("scan_counts", 0.0), 4),
+                 fit_ms=round(kt.get("cluster_fit", 0.0) + kt.get("bucket_layers", 0.0), 4))
+        if n_ev is None:
+            import oracle
+            tab = oracle.Tables(spec)
+            ev = batch.event(0)
+            opk = oracle.peaks(tab, oracle.vote_mask(tab, ev.layer, ev.phi))
+            t1 = time.perf_counter()
+            _, ocl = oracle.clusters(tab, opk)
+            oracle.fit(tab, ev.layer, ev.phi, opk, ocl)
+            r["oracle_s"] = round(time.perf_counter() - t1, 3)
+        out[name] = r
+        del ctx, pk, lab, cl, fits
+        torch.cuda.empty_cache()
+    return out
+
+
 def _oracle_event(args):
     spec, layer, phi = args
     import oracle
@@ -506,6 +560,12 @@ def main():
         res["count_form"] = bench_count_form(H, torch)
         log("count form: " + ", ".join(f"{x['tracks']} trk {x['ms_per_event']} ms"
                                        for x in res["count_form"]["sweep"]))
+    if not args.no_batched:
+        log("candidate confirmation: clusters and fit ...")
+        res["confirmation"] = bench_confirmation(H, torch)
+        log("confirmation: " + ", ".join(f"{k.split('_')[0]} {v['clusters']} clusters "
+                                          f"{v['clusters_ms']}+{v['fit_ms']} ms"
+                                          for k, v in res["confirmation"].items()))
     if not args.no_serving:
         from paper_1310_7556_amd import serve
         log("c5 serving sweep ...")

@@ -189,7 +189,9 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     c->rows = spec->n_d0 * spec->n_qpt;
     c->cells = uint64_t(c->rows) * spec->n_phi;
     const bool rz = spec->n_z0 > 0;
-    c->bucket_bits = rz ? std::min(c->log2_phi + 2, kMaxBucketBits) : 0;
+    // azimuth buckets: member search of the rz stage and of the cluster fit
+    const bool buckets = rz || limits->max_peaks > 0;
+    c->bucket_bits = buckets ? std::min(c->log2_phi + 2, kMaxBucketBits) : 0;
 
     // host tables
     const size_t nOV = size_t(spec->n_layers) * c->rows;
@@ -224,13 +226,13 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     const uint32_t L = spec->n_layers;
     c->n_peak_tiles = std::max<uint64_t>(uint64_t(E) * c->rows, E);
     c->scan_blocks_max = scan_blocks(c->n_peak_tiles);
-    const size_t nb = rz ? (size_t(1) << c->bucket_bits) + 1 : 0;
+    const size_t nb = buckets ? (size_t(1) << c->bucket_bits) + 1 : 0;
     const size_t ncand = rz ? size_t(E) * spec->rz_max_candidates : 0;
     const size_t rzh = rz ? size_t(c->n_cu) * kMaxRzWavesPerCu * spec->n_z0 : 0;
     bool ok = dev_alloc(&c->d_O, nOV + kOPad) && dev_alloc(&c->d_V, nOV) && dev_alloc(&c->d_Z, Z.size()) &&
               dev_alloc(&c->d_Zl, Zl.size()) &&
               dev_alloc(&c->d_phi_a, H) && dev_alloc(&c->d_z_a, rz ? H : 0) &&
-              dev_alloc(&c->d_phi_b, rz ? H : 0) && dev_alloc(&c->d_z_b, rz ? H : 0) &&
+              dev_alloc(&c->d_phi_b, buckets ? H : 0) && dev_alloc(&c->d_z_b, rz ? H : 0) &&
               dev_alloc(&c->d_layer_off, size_t(E) * (L + 1)) &&
               dev_alloc(&c->d_bucket_off, size_t(E) * L * nb) && dev_alloc(&c->d_order, E) &&
               dev_alloc(&c->d_counters, 64) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&

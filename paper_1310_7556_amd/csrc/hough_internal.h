@@ -52,7 +52,7 @@ struct hough_ctx {
     uint32_t shift = 0;          // 32 - log2_phi
     uint32_t rows = 0;           // n_d0 * n_qpt
     uint64_t cells = 0;          // rows * n_phi
-    uint32_t bucket_bits = 0;    // rz member search buckets (0 when no rz)
+    uint32_t bucket_bits = 0;    // member search buckets (0 without rz and without max_peaks)
 
     // tables (device)
     uint32_t *d_O = nullptr;     // [L][rows] + kOPad zero entries
@@ -110,7 +110,7 @@ void prof_end(hough_ctx *c, hipStream_t s, KernelTimer *t);
 // ---- launchers (each returns the HIP status of its launch) --------------
 hipError_t launch_fill_u32(hough_ctx *c, uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_bucket_layers(hough_ctx *c, const hough_hits *h, bool with_z, hipStream_t s);
-hipError_t launch_bucket_phi(hough_ctx *c, const hough_hits *h, hipStream_t s);
+hipError_t launch_bucket_phi(hough_ctx *c, const hough_hits *h, hipStream_t s, bool with_z = true);
 hipError_t launch_event_order(hough_ctx *c, const hough_hits *h, hipStream_t s);
 hipError_t launch_vote(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
 hipError_t launch_vote_count(hough_ctx *c, const hough_hits *h, uint32_t *counts, hipStream_t s);

@@ -84,7 +84,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *tmp)
 }
 
 // One workgroup per (event, layer): counting sort of the layer's hits by the
-// top `bits` bits of phi.  bucket_off[(e * L + l) * (NB + 1) + i] = start of
+// top `bits` bits of phi (z moved along unless out_z is null).  bucket_off[(e * L + l) * (NB + 1) + i] = start of
 // bucket i relative to the event start.
 __global__ void __launch_bounds__(1024)
 k_bucket_phi(const uint32_t *__restrict__ in_phi, const int32_t *__restrict__ in_z,
@@ -113,7 +113,7 @@ k_bucket_phi(const uint32_t *__restrict__ in_phi, const int32_t *__restrict__ in
         const uint32_t ph = in_phi[b + i];
         const uint32_t pos = s0 + atomicAdd(&hist[ph >> sh], 1u);
         out_phi[b + pos] = ph;
-        out_z[b + pos] = in_z[b + i];
+        if (out_z) out_z[b + pos] = in_z[b + i];
     }
 }
 
@@ -167,14 +167,15 @@ hipError_t launch_bucket_layers(hough_ctx *c, const hough_hits *h, bool with_z, 
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_phi(hough_ctx *c, const hough_hits *h, hipStream_t s)
+hipError_t launch_bucket_phi(hough_ctx *c, const hough_hits *h, hipStream_t s, bool with_z)
 {
     if (h->n_events == 0) return hipSuccess;
     KernelTimer t;
     prof_begin(c, "bucket_phi", s, &t);
     hipLaunchKernelGGL(k_bucket_phi, dim3(h->n_events * c->spec.n_layers), dim3(1024), 0, s,
                        c->d_phi_a, c->d_z_a, h->event_offsets, h->n_hits, c->d_layer_off,
-                       c->spec.n_layers, c->bucket_bits, c->d_phi_b, c->d_z_b, c->d_bucket_off);
+                       c->spec.n_layers, c->bucket_bits, c->d_phi_b, with_z ? c->d_z_b : nullptr,
+                       c->d_bucket_off);
     prof_end(c, s, &t);
     return hipGetLastError();
 }

@@ -143,53 +143,63 @@ __global__ void __launch_bounds__(256) k_cl_link(ClParams P)
         const uint32_t c = P.pk[i].x;
         const uint32_t p = c & pmask, row = c >> P.log2_phi;
         const uint32_t k = row % P.n_qpt, d = row / P.n_qpt;
-        // search the neighbour cell c2 where it can be: after i when larger
-        // (at most c2 - c places on), before i when smaller (phi0 wrap)
+        // first index in [b, t) whose cell is >= key (cells ascend)
+        auto lower = [&](uint64_t b, uint64_t t, uint32_t key) {
+            while (b < t) {
+                const uint64_t m = (b + t) >> 1;
+                if (P.pk[m].x < key) b = m + 1;
+                else t = m;
+            }
+            return b;
+        };
+        // one neighbour cell c2, wherever it is: after i when larger (at
+        // most c2 - c places on), before i when smaller (phi0 wrap)
         auto try_cell = [&](uint32_t c2) {
-            int64_t j;
+            uint64_t b, t;
             if (c2 > c) {
-                const uint64_t b = i + 1, t = min(hi, i + 1 + uint64_t(c2 - c));
-                if (b >= t) return;
-                uint64_t l = b, h = t;
-                while (l < h) {
-                    const uint64_t m = (l + h) >> 1;
-                    if (P.pk[m].x < c2) l = m + 1;
-                    else h = m;
-                }
-                j = (l < t && P.pk[l].x == c2) ? int64_t(l) : -1;
+                b = i + 1;
+                t = min(hi, i + 1 + uint64_t(c2 - c));
             } else if (c2 < c) {
                 const uint64_t back = uint64_t(c - c2);
-                const uint64_t b = i - lo > back ? i - back : lo, t = i;
-                if (b >= t) return;
-                uint64_t l = b, h = t;
-                while (l < h) {
-                    const uint64_t m = (l + h) >> 1;
-                    if (P.pk[m].x < c2) l = m + 1;
-                    else h = m;
-                }
-                j = (l < t && P.pk[l].x == c2) ? int64_t(l) : -1;
+                b = i - lo > back ? i - back : lo;
+                t = i;
             } else {
                 return;
             }
-            if (j >= 0) cl_unite(P.par, uint32_t(i), uint32_t(j));
+            if (b >= t) return;
+            const uint64_t j = lower(b, t, c2);
+            if (j < t && P.pk[j].x == c2) cl_unite(P.par, uint32_t(i), uint32_t(j));
         };
-        const uint32_t pp = (p + 1) & pmask, pm = (p - 1) & pmask;
-        const uint32_t rowc = row << P.log2_phi;
-        try_cell(rowc | pp);
-        if (k + 1 < P.n_qpt) {
-            const uint32_t r1 = (row + 1) << P.log2_phi;
-            try_cell(r1 | pm);
-            try_cell(r1 | p);
-            try_cell(r1 | pp);
+        // three consecutive cells ca .. ca + 2 of a later row (no wrap inside):
+        // one search, then at most three list entries
+        auto try_triple = [&](uint32_t ca) {
+            const uint64_t t = min(hi, i + 1 + uint64_t(ca + 2 - c));
+            if (i + 1 >= t) return;
+            for (uint64_t q = lower(i + 1, t, ca); q < t; ++q) {
+                if (P.pk[q].x > ca + 2) break;
+                cl_unite(P.par, uint32_t(i), uint32_t(q));
+            }
+        };
+        auto try_row = [&](uint32_t rbase) {
+            if (p != 0 && p != pmask) {
+                try_triple(rbase | (p - 1));
+            } else {
+                try_cell(rbase | ((p - 1) & pmask));
+                try_cell(rbase | p);
+                try_cell(rbase | ((p + 1) & pmask));
+            }
+        };
+        if (p != pmask) {
+            if (i + 1 < hi && P.pk[i + 1].x == c + 1) cl_unite(P.par, uint32_t(i), uint32_t(i + 1));
+        } else {
+            try_cell(row << P.log2_phi);                // (k, 0) across the wrap
         }
+        if (k + 1 < P.n_qpt) try_row((row + 1) << P.log2_phi);
         if (d + 1 < P.n_d0) {
             for (int dk = -1; dk <= 1; ++dk) {
                 const int k2 = int(k) + dk;
                 if (k2 < 0 || k2 >= int(P.n_qpt)) continue;
-                const uint32_t r2 = ((d + 1) * P.n_qpt + uint32_t(k2)) << P.log2_phi;
-                try_cell(r2 | pm);
-                try_cell(r2 | p);
-                try_cell(r2 | pp);
+                try_row(((d + 1) * P.n_qpt + uint32_t(k2)) << P.log2_phi);
             }
         }
     }
@@ -267,6 +277,10 @@ __global__ void __launch_bounds__(kClThreads) k_cl_rank(ClParams P)
 }
 
 // Labels (cluster index within the event), member sums, event offsets.
+// Whole waves step through the list together: runs of adjacent lanes in one
+// cluster (a flat plateau along phi0 is a run of consecutive list entries)
+// are summed by segmented shuffles first, and the run's last lane issues the
+// atomics once for the run.
 __global__ void __launch_bounds__(256) k_cl_acc(ClParams P)
 {
     const uint64_t n = n_stored(P);
@@ -276,29 +290,57 @@ __global__ void __launch_bounds__(256) k_cl_acc(ClParams P)
         const uint64_t s = min(P.poff[e], n);
         P.coff[e] = s < n ? P.rank[s] : total;
     }
-    const uint32_t pmask = P.n_phi - 1;
+    const uint32_t pmask = P.n_phi - 1, lane = threadIdx.x & 63;
     const int32_t half = int32_t(P.n_phi >> 1);
-    for (uint64_t i = g0; i < n; i += gs) {
-        const uint32_t e = event_of(P, n, i);
-        const uint64_t lo = min(P.poff[e], i);
-        const uint32_t r = P.par[i];
-        const uint32_t cid = P.rank[r];
-        P.par[i] = cid - P.rank[lo];
-        if (r == uint32_t(i) || cid >= P.cl_cap) continue;
-        const uint32_t c = P.pk[i].x, y = P.pk[i].y, cr = P.pk[r].x;
-        const uint32_t row = c >> P.log2_phi, rowr = cr >> P.log2_phi;
-        const int32_t dk = int32_t(row % P.n_qpt) - int32_t(rowr % P.n_qpt);
-        const int32_t dd = int32_t(row / P.n_qpt) - int32_t(rowr / P.n_qpt);
-        int32_t dp = int32_t((c - cr) & pmask);
-        if (dp >= half) dp -= int32_t(P.n_phi);
-        hough_cluster *h = P.cl + cid;
-        // n_peaks (low word, never carries) and sum_dk (high word) in one add
-        atomicAdd(reinterpret_cast<unsigned long long *>(&h->n_peaks),
-                  (static_cast<unsigned long long>(uint32_t(dk)) << 32) | 1ull);
-        if (dp) atomicAdd(&h->sum_dp, dp);
-        if (dd) atomicAdd(&h->sum_dd, dd);
-        const uint32_t m = y & 0xFFFFu, mr = P.pk[r].y & 0xFFFFu;
-        if (m & ~mr) atomicOr(reinterpret_cast<uint32_t *>(&h->popcount), m << 16);
+    const uint64_t lanes_below = lane == 63 ? ~uint64_t(0) : (uint64_t(2) << lane) - 1;
+    for (uint64_t base = g0 - lane; base < n; base += gs) {
+        const uint64_t i = base + lane;
+        uint32_t key = 0xFFFFFFFFu, cnt = 0, m = 0, r = 0;
+        int32_t dk = 0, dp = 0, dd = 0;
+        if (i < n) {
+            const uint32_t e = event_of(P, n, i);
+            const uint64_t lo = min(P.poff[e], i);
+            r = P.par[i];
+            const uint32_t cid = P.rank[r];
+            P.par[i] = cid - P.rank[lo];
+            if (r != uint32_t(i) && cid < P.cl_cap) {
+                const uint32_t c = P.pk[i].x, cr = P.pk[r].x;
+                const uint32_t row = c >> P.log2_phi, rowr = cr >> P.log2_phi;
+                key = cid;
+                cnt = 1;
+                dk = int32_t(row % P.n_qpt) - int32_t(rowr % P.n_qpt);
+                dd = int32_t(row / P.n_qpt) - int32_t(rowr / P.n_qpt);
+                dp = int32_t((c - cr) & pmask);
+                if (dp >= half) dp -= int32_t(P.n_phi);
+                m = P.pk[i].y & 0xFFFFu;
+            }
+        }
+        // segmented inclusive sums over runs of equal keys
+        const uint32_t prev = __shfl_up(key, 1, 64);
+        const uint64_t heads = __ballot(lane == 0 || prev != key);
+        const uint32_t start = 63u - uint32_t(__clzll(heads & lanes_below));
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t c2 = __shfl_up(cnt, d, 64), m2 = __shfl_up(m, d, 64);
+            const int32_t k2 = __shfl_up(dk, d, 64), p2 = __shfl_up(dp, d, 64), d2 = __shfl_up(dd, d, 64);
+            if (lane >= start + d) {
+                cnt += c2;
+                m |= m2;
+                dk += k2;
+                dp += p2;
+                dd += d2;
+            }
+        }
+        const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1u);
+        if (tail && key != 0xFFFFFFFFu) {
+            hough_cluster *h = P.cl + key;
+            // n_peaks (low word, never carries) and sum_dk (high word) in one add
+            atomicAdd(reinterpret_cast<unsigned long long *>(&h->n_peaks),
+                      (static_cast<unsigned long long>(uint32_t(dk)) << 32) | cnt);
+            if (dp) atomicAdd(&h->sum_dp, dp);
+            if (dd) atomicAdd(&h->sum_dd, dd);
+            const uint32_t mr = P.pk[r].y & 0xFFFFu;
+            if (m & ~mr) atomicOr(reinterpret_cast<uint32_t *>(&h->popcount), m << 16);
+        }
     }
 }
 

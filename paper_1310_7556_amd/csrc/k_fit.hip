@@ -11,9 +11,9 @@
 //
 // Members are the hits that voted into the cluster's first peak cell; the
 // reference azimuth is the centre of that cell's phi0 bin.  One wave per
-// cluster: pass 1 sums x'^2, x' r^2, r^4, x' y', y' r^2 over the members of
-// the event's layer-grouped hits (lanes over hits, one layer at a time, so
-// the row offset is wave-uniform), pass 2 the squared residuals of the
+// cluster: pass 1 sums x'^2, x' r^2, r^4, x' y', y' r^2 over the members,
+// found in the few azimuth buckets per layer that cover the cell (hits
+// sorted by (layer, bucket) per event), pass 2 the squared residuals of the
 // solution; fp64 throughout, wave sums by a fixed butterfly.
 #include "hough_internal.h"
 
@@ -21,8 +21,9 @@ namespace hough {
 namespace {
 
 struct FitParams {
-    const uint32_t *phi_a;        // layer-grouped azimuths of all events
-    const uint32_t *layer_off;    // [E][L + 1] relative to the event start
+    const uint32_t *phi_b;        // hits grouped by (layer, azimuth bucket) per event
+    const uint32_t *bucket_off;   // [E][L][NB + 1] relative to the event start
+    uint32_t bucket_bits;
     const uint64_t *hoff;         // [E + 1] hit offsets
     uint64_t n_hits;
     const uint2 *pk;              // peak records
@@ -53,6 +54,73 @@ __device__ __forceinline__ uint32_t wave_sum_u(uint32_t v)
     return v;
 }
 
+// The member hits of cell (k, p) lie in a few azimuth buckets per layer.
+// Lane l < L finds layer l's bucket window (one range of the layer's
+// bucket-sorted hits, two when it wraps past 2 pi); a lane scan of the
+// window lengths concatenates them, and visit(layer lane, hit) walks the
+// concatenation with the lanes side by side.  Every shuffle runs on all
+// lanes; visit sees only hits that pass the membership test.
+struct Windows {
+    uint32_t o, hs1, len1, hs2, excl, total;
+};
+
+__device__ __forceinline__ Windows layer_windows(const FitParams &P, uint32_t e, uint32_t k, uint32_t p,
+                                                 uint32_t lane)
+{
+    const uint32_t nb = 1u << P.bucket_bits, bs = 32 - P.bucket_bits;
+    const uint64_t W = uint64_t(1) << P.shift, BW = uint64_t(1) << bs;
+    Windows w{};
+    uint32_t len2 = 0;
+    if (lane < P.n_layers) {
+        const size_t ti = size_t(lane) * P.n_qpt + k;
+        if (P.V[ti]) {
+            w.o = P.O[ti];
+            const uint32_t start = w.o + (p << P.shift);
+            const uint32_t b0 = start >> bs;
+            const uint32_t nbk = min(uint32_t(((uint64_t(start) & (BW - 1)) + W - 1) / BW + 1), nb);
+            const uint32_t *bl = P.bucket_off + (size_t(e) * P.n_layers + lane) * (nb + 1);
+            const uint32_t e1 = b0 + nbk;
+            w.hs1 = bl[b0];
+            if (e1 <= nb) {
+                w.len1 = bl[e1] - w.hs1;
+            } else {
+                w.len1 = bl[nb] - w.hs1;
+                w.hs2 = bl[0];
+                len2 = bl[e1 - nb] - w.hs2;
+            }
+        }
+    }
+    const uint32_t len = w.len1 + len2;
+    uint32_t incl = len;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        incl += lane >= d ? y : 0u;
+    }
+    w.excl = incl - len;
+    w.total = __shfl(incl, 63, 64);
+    return w;
+}
+
+template <typename Fn>
+__device__ __forceinline__ void for_members(const FitParams &P, const Windows &w, uint64_t eb, uint32_t p,
+                                            uint32_t lane, Fn &&visit)
+{
+    for (uint32_t g0 = 0; g0 < w.total; g0 += 64) {
+        const uint32_t gi = g0 + lane;
+        uint32_t ls = 0;
+        for (uint32_t q = 0; q < P.n_layers; ++q) ls = __shfl(w.excl, q, 64) <= gi ? q : ls;
+        const uint32_t local = gi - __shfl(w.excl, ls, 64);
+        const uint32_t l1 = __shfl(w.len1, ls, 64);
+        const uint32_t h1 = __shfl(w.hs1, ls, 64), h2 = __shfl(w.hs2, ls, 64);
+        const uint32_t o = __shfl(w.o, ls, 64);
+        if (gi < w.total) {
+            const uint32_t h = local < l1 ? h1 + local : h2 + (local - l1);
+            const uint32_t ph = P.phi_b[eb + h];
+            if (((ph - o) >> P.shift) == p) visit(ls, ph);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fit(FitParams P)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -61,7 +129,7 @@ __global__ void __launch_bounds__(256) k_fit(FitParams P)
     const uint64_t n_cl = min(P.coff[P.E], P.cl_cap);
     const double two_pi = 6.283185307179586476925286766559;
     const double turn_rad = two_pi / 4294967296.0;
-    const uint32_t pmask = P.n_phi - 1, L = P.n_layers;
+    const uint32_t pmask = P.n_phi - 1;
     for (uint64_t c = wave0; c < n_cl; c += waves) {
         // event of cluster c: largest e with start(e) <= c
         uint32_t lo = 0, hi = P.E;
@@ -87,29 +155,22 @@ __global__ void __launch_bounds__(256) k_fit(FitParams P)
             f.phi0_c = two_pi * fr;
 
             const uint64_t eb = min(P.hoff[e], P.n_hits);
-            const uint32_t *lof = P.layer_off + size_t(e) * (L + 1);
             const uint32_t ref = (p << P.shift) + (1u << (P.shift - 1));
+            const Windows w = layer_windows(P, e, k, p, lane);
             double sxx = 0, sxw = 0, sww = 0, sxy = 0, syw = 0;
             uint32_t m = 0;
-            for (uint32_t l = 0; l < L; ++l) {
-                const size_t ti = size_t(l) * P.n_qpt + k;
-                if (!P.V[ti]) continue;
-                const uint32_t o = P.O[ti];
-                const double r = P.r_mm[l], w = r * r;
-                for (uint32_t j = lof[l] + lane; j < lof[l + 1]; j += 64) {
-                    const uint32_t ph = P.phi_a[eb + j];
-                    if (((ph - o) >> P.shift) != p) continue;
-                    double sa, ca;
-                    sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
-                    const double x = r * ca, y = r * sa;
-                    sxx += x * x;
-                    sxw += x * w;
-                    sww += w * w;
-                    sxy += x * y;
-                    syw += y * w;
-                    ++m;
-                }
-            }
+            for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t ph) {
+                double sa, ca;
+                sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
+                const double r = P.r_mm[l], wr = r * r;
+                const double x = r * ca, y = r * sa;
+                sxx += x * x;
+                sxw += x * wr;
+                sww += wr * wr;
+                sxy += x * y;
+                syw += y * wr;
+                ++m;
+            });
             sxx = wave_sum(sxx);
             sxw = wave_sum(sxw);
             sww = wave_sum(sww);
@@ -123,20 +184,13 @@ __global__ void __launch_bounds__(256) k_fit(FitParams P)
                 const double alpha = (sxw * sxy - sxx * syw) / det;
                 const double cosp = 1.0 / sqrt(1.0 + t * t);
                 double ss = 0;
-                for (uint32_t l = 0; l < L; ++l) {
-                    const size_t ti = size_t(l) * P.n_qpt + k;
-                    if (!P.V[ti]) continue;
-                    const uint32_t o = P.O[ti];
-                    const double r = P.r_mm[l], w = r * r;
-                    for (uint32_t j = lof[l] + lane; j < lof[l + 1]; j += 64) {
-                        const uint32_t ph = P.phi_a[eb + j];
-                        if (((ph - o) >> P.shift) != p) continue;
-                        double sa, ca;
-                        sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
-                        const double res = (r * sa - t * (r * ca) + alpha * w) * cosp;
-                        ss += res * res;
-                    }
-                }
+                for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t ph) {
+                    double sa, ca;
+                    sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
+                    const double r = P.r_mm[l];
+                    const double res = (r * sa - t * (r * ca) + alpha * (r * r)) * cosp;
+                    ss += res * res;
+                });
                 ss = wave_sum(ss);
                 double ph0 = fmod(double(ref) * turn_rad + atan(t), two_pi);
                 if (ph0 < 0) ph0 += two_pi;
@@ -158,10 +212,12 @@ hipError_t launch_fit(hough_ctx *c, const hough_hits *h, const hough_peak *peaks
 {
     if (h->n_events == 0 || capacity == 0) return hipSuccess;
     hipError_t err = launch_bucket_layers(c, h, false, s);
+    if (err == hipSuccess) err = launch_bucket_phi(c, h, s, false);
     if (err != hipSuccess) return err;
     FitParams P{};
-    P.phi_a = c->d_phi_a;
-    P.layer_off = c->d_layer_off;
+    P.phi_b = c->d_phi_b;
+    P.bucket_off = c->d_bucket_off;
+    P.bucket_bits = c->bucket_bits;
     P.hoff = h->event_offsets;
     P.n_hits = h->n_hits;
     P.pk = reinterpret_cast<const uint2 *>(peaks);
@@ -183,7 +239,7 @@ hipError_t launch_fit(hough_ctx *c, const hough_hits *h, const hough_peak *peaks
     P.qpt_lo = c->spec.qpt_lo;
     P.qpt_w = (c->spec.qpt_hi - c->spec.qpt_lo) / c->spec.n_qpt;
     P.inv_curv = 1.0 / (0.299792458e-3 * c->spec.b_tesla);
-    const uint64_t blocks = std::min<uint64_t>((capacity + 3) / 4, uint64_t(c->n_cu) * 8);
+    const uint64_t blocks = std::min<uint64_t>((capacity + 3) / 4, uint64_t(c->n_cu) * 16);
     KernelTimer t;
     prof_begin(c, "cluster_fit", s, &t);
     hipLaunchKernelGGL(k_fit, dim3(uint32_t(std::max<uint64_t>(blocks, 1))), dim3(256), 0, s, P);
