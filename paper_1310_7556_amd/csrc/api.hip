@@ -207,7 +207,7 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
         // uint32 difference u = z - zl is < span exactly when 0 <= z - zl <
         // span for every int32 z; the bin is then one multiply-high
         const int64_t span = int64_t(spec->z0_hi_um) - int64_t(spec->z0_lo_um);
-        const BinMagic bm = make_binmagic(uint64_t(span), spec->n_z0);
+        const BinMagic bm = make_binmagic_min(uint64_t(span), spec->n_z0);
         bool ok = bm.ok;
         Zl.resize(Z.size());
         for (size_t i = 0; ok && i < Z.size(); ++i) {

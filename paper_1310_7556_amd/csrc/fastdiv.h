@@ -69,6 +69,41 @@ inline BinMagic make_binmagic(uint64_t span, uint32_t nbins)
     return b;
 }
 
+// The sufficient condition above is far from necessary.  A smaller shift s'
+// (down to 0, which saves an instruction per use) is accepted when the
+// multiply-high is exact on every u in [0, span): the approximation
+// f(u) = (u * m') >> (32 + s') is non-decreasing, so it equals the step
+// function floor(u * nbins / span) everywhere iff it does at both ends of
+// every step [ceil(k span / nbins), ceil((k + 1) span / nbins) - 1].
+inline bool binmagic_exact(uint64_t span, uint32_t nbins, uint32_t m, uint32_t s)
+{
+    auto f = [&](uint64_t u) { return ((u * m) >> 32) >> s; };
+    for (uint64_t k = 0; k < nbins; ++k) {
+        const uint64_t a = (k * span + nbins - 1) / nbins;
+        const uint64_t b = ((k + 1) * span + nbins - 1) / nbins;
+        if (a >= b) continue;
+        if (f(a) != k || f(b - 1) != k) return false;
+    }
+    return true;
+}
+
+inline BinMagic make_binmagic_min(uint64_t span, uint32_t nbins)
+{
+    BinMagic b = make_binmagic(span, nbins);
+    if (!b.ok) return b;
+    for (uint32_t s = 0; s < b.s; ++s) {
+        const unsigned __int128 num = (unsigned __int128)nbins << (32 + s);
+        const unsigned __int128 m = (num + span - 1) / span;
+        if (m >= ((unsigned __int128)1 << 32)) continue;
+        if (binmagic_exact(span, nbins, uint32_t(m), s)) {
+            b.m = uint32_t(m);
+            b.s = s;
+            return b;
+        }
+    }
+    return b;
+}
+
 HOUGH_HD inline uint32_t binmagic_apply(uint32_t u, uint32_t m, uint32_t s)
 {
     return uint32_t(((uint64_t(u) * m) >> 32) >> s);

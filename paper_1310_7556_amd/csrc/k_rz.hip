@@ -18,11 +18,13 @@
 //      wave prefix over window lengths flattens all layers' scanned hits,
 //      and one ballot-compacted pass copies the members' z (grouped by layer)
 //      into LDS;
-//   2. per cot bin, per layer, per member: u = z - (Z + z0_lo) in uint32,
-//      in range iff u < span, bin by one multiply-high (BinMagic), and an
-//      LDS atomic add on a lane-private packed counter (8- or 16-bit) whose
+//   2. per cot bin, per member: u = z - (Z + z0_lo) in uint32, bin by one
+//      multiply-high (BinMagic, no shift where that is exact), which maps
+//      every u >= span past the last bin into a trash counter, and an LDS
+//      atomic add on a lane-private packed counter (8- or 16-bit) whose
 //      return value gives the running count without a read-modify-write
-//      chain;
+//      chain; members are padded to a multiple of 8 with ones that never
+//      vote;
 //   3. the counters are cleared wholesale with 16-byte stores.
 // A candidate with more members than the LDS list or the counter width
 // holds takes the slow path: a uint32 histogram in global scratch, one cot
@@ -187,6 +189,41 @@ struct RzCand {
     const uint32_t *bo;
 };
 
+// Peak record of candidate c (event search, candidate index, record load).
+__device__ __forceinline__ uint2 rz_record(const RzParams &P, uint64_t c)
+{
+    uint32_t lo = 0, hi = P.n_events;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (P.roff[mid] <= c) lo = mid; else hi = mid;
+    }
+    const uint32_t e = uni(lo);
+    const uint32_t pk = P.cap ? uni(P.cand[c]) : uni(uint32_t(c - P.roff[e]));
+    return P.peaks[uni64(P.poff[e] + pk)];
+}
+
+// rz_decode with the peak record already fetched.
+__device__ __forceinline__ RzCand rz_decode_rec(const RzParams &P, uint64_t c, uint2 rec)
+{
+    RzCand r;
+    const uint32_t nb = 1u << P.bucket_bits;
+    uint32_t lo = 0, hi = P.n_events;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (P.roff[mid] <= c) lo = mid; else hi = mid;
+    }
+    r.e = uni(lo);
+    const uint32_t local = uni(uint32_t(c - P.roff[r.e]));
+    r.pk = P.cap ? uni(P.cand[c]) : local;
+    const uint32_t cell = uni(rec.x);
+    r.mask = uni(rec.y & 0xFFFFu);
+    r.k = (cell >> P.log2phi) % P.n_qpt;
+    r.p = cell & (P.nphi - 1);
+    r.eb = uni64(min(P.offs[r.e], P.n_hits));
+    r.bo = P.bucket_off + size_t(r.e) * P.n_layers * (nb + 1);
+    return r;
+}
+
 __device__ __forceinline__ RzCand rz_decode(const RzParams &P, uint64_t c)
 {
     RzCand r;
@@ -270,10 +307,12 @@ __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
 // LDS layout of the fast kernel, in dwords.
 __host__ __device__ inline uint32_t rz_fast_lds_dwords(uint32_t hw, uint32_t mcap)
 {
-    return hw * 64 + 96 + 32 + mcap + (mcap + 3) / 4;
+    // member z and layer arrays hold mcap members plus up to 7 padding ones
+    return hw * 64 + 96 + 32 + (mcap + 8) + (mcap + 8 + 3) / 4;
 }
 
-template <int BITS>
+// SHIFT: the bin multiply needs its extra right shift (bs > 0).
+template <int BITS, bool SHIFT>
 __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
 {
     constexpr uint32_t PACK = 32 / BITS;           // counters per dword
@@ -285,11 +324,10 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
     uint32_t *lay = hist + P.hw * 64;                // [5][16] per-layer windows
     uint32_t *loff = lay + 96;                       // [L + 1] member offsets per layer
     int32_t *mz = reinterpret_cast<int32_t *>(loff + 32);    // [mcap] member z
-    uint8_t *ml = reinterpret_cast<uint8_t *>(mz + P.mcap);  // [mcap] member layer
+    uint8_t *ml = reinterpret_cast<uint8_t *>(mz + P.mcap + 8);  // [mcap + 8] member layer
     const uint32_t lim = min(P.mcap, FIELD);
     const uint32_t nb = 1u << P.bucket_bits, bsh = 32 - P.bucket_bits;
     const uint32_t nl = P.n_layers;
-    const uint32_t span = uint32_t(P.span);
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
     for (uint32_t i = lane; i < P.hw * 64; i += 64) hist[i] = 0;
     __syncthreads();
@@ -300,9 +338,21 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
         const uint64_t c0 = uni(atomicAdd(P.counter, lane == 0 ? kRzChunk : 0u));
         if (c0 >= total) break;
         const uint64_t c1 = min(c0 + kRzChunk, total);
+        // the next candidate's peak record is fetched while the current one
+        // is processed, so its latency overlaps the current loads
+        uint2 nrec = rz_record(P, c0);
       for (uint64_t c = c0; c < c1; ++c) {
-        const RzCand r = rz_decode(P, c);
+        const uint2 rec = nrec;
+        if (c + 1 < c1) nrec = rz_record(P, c + 1);
+        const RzCand r = rz_decode_rec(P, c, rec);
         const uint32_t k = r.k, p = r.p;
+        // all layers' (Z + z0_lo) for this lane's first cot bin, issued now
+        // so that they arrive with the member search's loads
+        const int32_t *zrow = P.Zl + size_t(k) * nl * P.n_cot;
+        uint32_t zr[kMaxLayers], zn[kMaxLayers];
+#pragma unroll
+        for (uint32_t l = 0; l < kMaxLayers; ++l)
+            zr[l] = l < nl ? uint32_t(zrow[size_t(l) * P.n_cot + min(lane, P.n_cot - 1)]) : 0u;
 
         // 1a. lane l < L: the azimuth-bucket window of layer l (one or two
         // ranges of the (layer, bucket)-sorted hits, two when it wraps)
@@ -356,9 +406,11 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
                 const uint32_t local = gi - lay[ls];
                 const uint32_t l1 = lay[16 + ls];
                 const uint32_t h = local < l1 ? lay[32 + ls] + local : lay[48 + ls] + (local - l1);
+                // z is loaded with phi (not after the test) to save a round trip
                 const uint32_t ph = P.phi[r.eb + h];
+                const int32_t zh = P.z[r.eb + h];
                 is_m = ((ph - lay[64 + ls]) >> P.shift) == p;
-                if (is_m) zv = P.z[r.eb + h];
+                zv = is_m ? zh : 0;
             }
             const uint64_t bal = __ballot(is_m);
             const uint32_t pos = nm + __popcll(bal & ((1ull << lane) - 1ull));
@@ -368,69 +420,73 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
             }
             nm += __popcll(bal);
         }
+        // pad the member list to a multiple of 8 with members that never
+        // vote: layer 15 is unused (n_layers < 16 on this path), so its
+        // (Z + z0_lo) register is 0, and z = 0xFFFFFFFF is then out of range
+        // for every cot bin
+        const uint32_t np8 = (nm + 7u) & ~7u;
+        if (nm <= lim && lane < np8 - nm) {
+            mz[nm + lane] = -1;
+            ml[nm + lane] = uint8_t(kMaxLayers - 1);
+        }
         __syncthreads();
 
         uint32_t best_c = 0, best_j = lane, best_b = 0;
         if (nm <= lim) {
-            const int32_t *zrow = P.Zl + size_t(k) * nl * P.n_cot;
-            // all layers' (Z + z0_lo) for this lane's cot bin: loaded for the
-            // next pass while the current one counts (one memory latency per
-            // candidate instead of one per pass)
-            uint32_t zr[kMaxLayers], zn[kMaxLayers];
-#pragma unroll
-            for (uint32_t l = 0; l < kMaxLayers; ++l)
-                zr[l] = l < nl ? uint32_t(zrow[size_t(l) * P.n_cot + min(lane, P.n_cot - 1)]) : 0u;
+            // the next pass's (Z + z0_lo) values are loaded while the current
+            // one counts (one memory latency per candidate, not per pass)
             for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 64) {
                 const uint32_t j = j0 + lane;
                 const bool jv = j < P.n_cot;
-                // lanes past the last cot bin count nothing (their span is 0)
-                const uint32_t lspan = jv ? span : 0u;
-                // running maximum of key = count << 16 | (0xFFFF - bin): the
-                // largest key has the largest count, ties to the smallest bin
-                uint32_t run = 0;
                 const uint32_t jn = min(j + 64, P.n_cot - 1);
                 const bool more = j0 + 64 < P.n_cot;
 #pragma unroll
                 for (uint32_t l = 0; l < kMaxLayers; ++l)
                     zn[l] = (more && l < nl) ? uint32_t(zrow[size_t(l) * P.n_cot + jn]) : 0u;
-                // one member's vote, straight-line integer code: in-range
-                // test, bin, lane-private packed counter, running maximum
-                auto bin_of = [&](uint32_t zm, uint32_t zl, uint32_t &b, uint32_t &sh, uint32_t &inc) {
-                    const uint32_t u = zm - zl;
-                    const uint32_t ok = u < lspan ? 1u : 0u;
-                    b = min(__umulhi(u, P.bm) >> P.bs, P.n_z0 - 1);
-                    sh = (b & (PACK - 1)) * BITS;
-                    inc = ok << sh;
-                };
-                auto take = [&](uint32_t old, uint32_t b, uint32_t sh, uint32_t inc) {
-                    const uint32_t key = ((((old >> sh) & FIELD) + 1u) << 16) | (0xFFFFu - b);
-                    run = max(run, inc ? key : 0u);
-                };
-                // all members in one flat loop, four per step: one 16-byte
-                // LDS read gives four z, one 4-byte read their four layers
-                // (so (Z + z0_lo) is a register-indexed move), then four
-                // counter atomics in flight and four running-max updates
+                // all members in one flat loop, eight per step: two 16-byte
+                // LDS reads give eight z, two 4-byte reads their layers (so
+                // (Z + z0_lo) is a register-indexed move).  Per member: the
+                // bin b = min(mulhi(u, m), n_z0) of u = z - (Z + z0_lo) --
+                // the multiply-high maps every u >= span (out of range, a
+                // padding member, or a lane past the last cot bin whose
+                // result is dropped) to n_z0 or above, so those votes land in
+                // a trash counter past the last bin -- then the lane-private
+                // packed counter atomic and the running maximum of the signed
+                // key (count - 1) * 2^16 - b over in-range votes (largest
+                // count wins, ties to the smallest bin)
                 const uint4 *mz4 = reinterpret_cast<const uint4 *>(mz);
                 const uint32_t *ml4 = reinterpret_cast<const uint32_t *>(ml);
-                uint32_t m = 0;
-                for (; m + 4 <= nm; m += 4) {
-                    const uint4 zq = mz4[m >> 2];
-                    const uint32_t lq = uni(ml4[m >> 2]);
-                    const uint32_t zm[4] = {zq.x, zq.y, zq.z, zq.w};
-                    uint32_t b[4], sh[4], inc[4], old[4];
+                // this lane's counter column (row stride 64 dwords)
+                uint32_t *col = hist + lane;
+                int32_t run = INT32_MIN;
+                for (uint32_t m = 0; m < np8; m += 8) {
+                    const uint4 za = mz4[m >> 2], zb = mz4[(m >> 2) + 1];
+                    const uint32_t la = uni(ml4[m >> 2]), lb = uni(ml4[(m >> 2) + 1]);
+                    const uint32_t zm[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+                    uint32_t b[8], sh[8], old[8];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) bin_of(zm[q], zr[(lq >> (8 * q)) & 0xFFu], b[q], sh[q], inc[q]);
+                    for (int q = 0; q < 8; ++q) {
+                        const uint32_t lq = ((q < 4 ? la : lb) >> (8 * (q & 3))) & 0xFFu;
+                        const uint32_t u = zm[q] - zr[lq];
+                        uint32_t t = __umulhi(u, P.bm);
+                        if (SHIFT) t >>= P.bs;
+                        b[q] = min(t, P.n_z0);
+                        sh[q] = b[q] << (BITS == 8 ? 3 : 4);   // field offset, taken mod 32
+                    }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) old[q] = atomicAdd(&hist[(b[q] >> PSH) * 64 + lane], inc[q]);
+                    for (int q = 0; q < 8; ++q) {
+                        // counter dword (b >> PSH) of this lane's column
+                        old[q] = atomicAdd(col + ((b[q] >> PSH) << 6), 1u << (sh[q] & 31u));
+                    }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) take(old[q], b[q], sh[q], inc[q]);
+                    for (int q = 0; q < 8; ++q) {
+                        const int32_t key = int32_t(__builtin_amdgcn_ubfe(old[q], sh[q], BITS) << 16) - int32_t(b[q]);
+                        run = b[q] < P.n_z0 ? max(run, key) : run;
+                    }
                 }
-                for (; m < nm; ++m) {
-                    uint32_t b, sh, inc;
-                    bin_of(uint32_t(mz[m]), zr[uni(ml[m])], b, sh, inc);
-                    take(atomicAdd(&hist[(b >> PSH) * 64 + lane], inc), b, sh, inc);
-                }
-                const uint32_t bc = run >> 16, bb = 0xFFFFu - (run & 0xFFFFu);
+                const int32_t fld = (run + 0xFFFF) >> 16;
+                const uint32_t bc = run == INT32_MIN ? 0u : uint32_t(fld) + 1u;
+                const uint32_t bb = uint32_t((fld << 16) - run);
 #pragma unroll
                 for (uint32_t l = 0; l < kMaxLayers; ++l) zr[l] = zn[l];
                 // clear all counters, 16 bytes per lane per store; a store
@@ -591,7 +647,8 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     // event) stay well below 255; candidates that exceed it use the slow path
     const double per_cell = double(h->n_hits) / double(std::max<uint32_t>(E, 1)) / double(g.n_phi);
     uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 8u : 16u);
-    const uint32_t hw = (g.n_z0 + (32 / bits) - 1) / (32 / bits);
+    // counter dwords per lane: bins 0 .. n_z0 - 1 plus the trash bin n_z0
+    const uint32_t hw = g.n_z0 / (32 / bits) + 1;
     // member list: 256 with 8-bit counters (their limit is 255), else as many
     // as fit the LDS budget, up to 4096
     uint32_t mcap = 256;
@@ -600,15 +657,21 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;
     }
     const size_t fast_lds = size_t(rz_fast_lds_dwords(hw, mcap)) * 4;
-    if (c->rz_fast && !c->tun.rz_slow_path && fast_lds <= c->max_lds) {
+    // the fast kernel pads member lists with a spare layer (n_layers < 16)
+    if (c->rz_fast && !c->tun.rz_slow_path && fast_lds <= c->max_lds && g.n_layers < kMaxLayers) {
         P.hw = hw;
         P.mcap = mcap;
         P.lds_ok = 0;
         prof_begin(c, "rz_vote", s, &t);
-        if (bits == 8)
-            hipLaunchKernelGGL(k_rz_vote_fast<8>, dim3(blocks), dim3(64), fast_lds, s, P);
+        const bool shift = P.bs != 0;
+        if (bits == 8 && shift)
+            hipLaunchKernelGGL((k_rz_vote_fast<8, true>), dim3(blocks), dim3(64), fast_lds, s, P);
+        else if (bits == 8)
+            hipLaunchKernelGGL((k_rz_vote_fast<8, false>), dim3(blocks), dim3(64), fast_lds, s, P);
+        else if (shift)
+            hipLaunchKernelGGL((k_rz_vote_fast<16, true>), dim3(blocks), dim3(64), fast_lds, s, P);
         else
-            hipLaunchKernelGGL(k_rz_vote_fast<16>, dim3(blocks), dim3(64), fast_lds, s, P);
+            hipLaunchKernelGGL((k_rz_vote_fast<16, false>), dim3(blocks), dim3(64), fast_lds, s, P);
         prof_end(c, s, &t);
         return hipGetLastError();
     }

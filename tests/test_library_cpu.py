@@ -113,9 +113,12 @@ int main() {
     const C cs[] = {{400000, 256}, {1, 1}, {3, 2}, {1000, 7}, {65535, 65535}, {4000000, 3},
                     {2000000001ull, 256}, {4294967295ull, 1}, {123457, 65535}};
     int tested = 0;
+    for (int variant = 0; variant < 2; ++variant)
     for (C c : cs) {
-        hough::BinMagic b = hough::make_binmagic(c.span, c.n);
+        // the proven shift, and the smallest shift whose step ends check out
+        hough::BinMagic b = variant ? hough::make_binmagic_min(c.span, c.n) : hough::make_binmagic(c.span, c.n);
         if (!b.ok) continue;
+        if (variant && c.span == 400000 && b.s != 0) { printf("no shift-free magic for 400000/256\n"); return 3; }
         tested++;
         auto check = [&](uint64_t u) {
             const uint64_t want = (unsigned __int128)u * c.n / c.span;
@@ -131,7 +134,7 @@ int main() {
             if (k > 4096) break;
         }
     }
-    return tested >= 4 ? 0 : 2;   // 400000/256, 3/2, 1000/7, 4e6/3 admit a 32-bit multiplier
+    return tested >= 8 ? 0 : 2;   // 400000/256, 3/2, 1000/7, 4e6/3 admit a 32-bit multiplier
 }
 ''')
     exe = tmp_path / "b"
