@@ -166,7 +166,7 @@ typedef struct {
     uint32_t vote_algo;             /* 0 = default (4), 1 = per-hit LDS atomics, 2 = global atomics,
                                        3 = hit-gap lists, 4 = bucket bounds (direct occupancy) */
     uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
-    uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 8 or 16 */
+    uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 4, 8 or 16 */
 } hough_tuning;
 
 /* ---- context --------------------------------------------------------- */

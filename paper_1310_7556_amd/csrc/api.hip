@@ -86,7 +86,8 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.vote_algo == 3 && !hough::gap_vote_usable(c)) return false;
     if (t.vote_algo == 4 && !hough::direct_vote_usable(c)) return false;
     if (t.rz_slow_path > 1) return false;
-    if (t.rz_counter_bits != 0 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16) return false;
+    if (t.rz_counter_bits != 0 && t.rz_counter_bits != 4 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16)
+        return false;
     return true;
 }
 

@@ -313,11 +313,14 @@ __host__ __device__ inline uint32_t rz_fast_lds_dwords(uint32_t hw, uint32_t mca
 
 // SHIFT: the bin multiply needs its extra right shift (bs > 0).
 template <int BITS, bool SHIFT>
-__global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))   // <= 128 VGPRs
+k_rz_vote_fast(RzParams P)
 {
     constexpr uint32_t PACK = 32 / BITS;           // counters per dword
-    constexpr uint32_t PSH = BITS == 8 ? 2 : 1;    // log2(PACK)
+    constexpr uint32_t PSH = BITS == 4 ? 3 : BITS == 8 ? 2 : 1;    // log2(PACK)
+    constexpr uint32_t BSH = BITS == 4 ? 2 : BITS == 8 ? 3 : 4;    // log2(BITS)
     constexpr uint32_t FIELD = (1u << BITS) - 1u;
+    static_assert(PACK == (1u << PSH) && BITS == (1u << BSH), "counter layout");
     HOUGH_DYNAMIC_LDS(uint32_t, lds);
     const uint32_t lane = threadIdx.x;
     uint32_t *hist = lds;                            // [hw][64] lane-private packed counters
@@ -325,7 +328,10 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
     uint32_t *loff = lay + 96;                       // [L + 1] member offsets per layer
     int32_t *mz = reinterpret_cast<int32_t *>(loff + 32);    // [mcap] member z
     uint8_t *ml = reinterpret_cast<uint8_t *>(mz + P.mcap + 8);  // [mcap + 8] member layer
-    const uint32_t lim = min(P.mcap, FIELD);
+    // 8- and 16-bit counters cannot overflow below FIELD members; 4-bit
+    // counters detect an overflow instead and send the candidate to the
+    // exact slow path
+    const uint32_t lim = BITS == 4 ? P.mcap : min(P.mcap, FIELD);
     const uint32_t nb = 1u << P.bucket_bits, bsh = 32 - P.bucket_bits;
     const uint32_t nl = P.n_layers;
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
@@ -432,6 +438,7 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
         __syncthreads();
 
         uint32_t best_c = 0, best_j = lane, best_b = 0;
+        bool ovf = false;                  // a 4-bit counter of a real bin overflowed
         if (nm <= lim) {
             // the next pass's (Z + z0_lo) values are loaded while the current
             // one counts (one memory latency per candidate, not per pass)
@@ -471,7 +478,7 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
                         uint32_t t = __umulhi(u, P.bm);
                         if (SHIFT) t >>= P.bs;
                         b[q] = min(t, P.n_z0);
-                        sh[q] = b[q] << (BITS == 8 ? 3 : 4);   // field offset, taken mod 32
+                        sh[q] = b[q] << BSH;   // field offset, taken mod 32
                     }
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
@@ -480,13 +487,17 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
                     }
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const int32_t key = int32_t(__builtin_amdgcn_ubfe(old[q], sh[q], BITS) << 16) - int32_t(b[q]);
+                        const uint32_t field = __builtin_amdgcn_ubfe(old[q], sh[q], BITS);
+                        const int32_t key = int32_t(field << 16) - int32_t(b[q]);
                         run = b[q] < P.n_z0 ? max(run, key) : run;
                     }
                 }
                 const int32_t fld = (run + 0xFFFF) >> 16;
                 const uint32_t bc = run == INT32_MIN ? 0u : uint32_t(fld) + 1u;
                 const uint32_t bb = uint32_t((fld << 16) - run);
+                // a count of FIELD + 1 can only come from a vote that found
+                // its field full: the counter overflowed
+                if (BITS == 4) ovf = ovf || bc > FIELD;
 #pragma unroll
                 for (uint32_t l = 0; l < kMaxLayers; ++l) zr[l] = zn[l];
                 // clear all counters, 16 bytes per lane per store; a store
@@ -499,7 +510,13 @@ __global__ void __launch_bounds__(64) k_rz_vote_fast(RzParams P)
                 __syncthreads();
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
             }
-        } else {
+        }
+        // an overflowed 4-bit count makes every result of this candidate
+        // suspect (a carry reaches the next bin): redo it exactly
+        if (nm > lim || (BITS == 4 && __ballot(ovf) != 0)) {
+            best_c = 0;
+            best_j = lane;
+            best_b = 0;
             rz_slow(P, r.eb, r.bo, k, p, r.mask, g, lane, best_c, best_j, best_b);
             if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
         }
@@ -642,16 +659,18 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     P.fd = make_fastdiv32(P.use32 ? uint32_t(P.span) : 1u);
     P.bm = c->rz_magic_m;
     P.bs = c->rz_magic_s;
-    const uint32_t blocks = rz_blocks(c);
-    // counter width: 8 bits when a cell's members (about hits / n_phi per
-    // event) stay well below 255; candidates that exceed it use the slow path
+    // counter width: 4 bits (overflow detected, then the slow path) when a
+    // cell's members (about hits / n_phi per event) are few, so that counts
+    // above 15 are rare and 16 waves fit a CU's LDS; 16 bits for dense events
     const double per_cell = double(h->n_hits) / double(std::max<uint32_t>(E, 1)) / double(g.n_phi);
-    uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 8u : 16u);
+    uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 4u : 16u);
+    const uint32_t blocks = c->tun.rz_waves_per_cu ? rz_blocks(c) : uint32_t(c->n_cu) * (bits == 4 ? 16u : 8u);
     // counter dwords per lane: bins 0 .. n_z0 - 1 plus the trash bin n_z0
     const uint32_t hw = g.n_z0 / (32 / bits) + 1;
-    // member list: 256 with 8-bit counters (their limit is 255), else as many
+    // member list: 192 with 4-bit counters (16 waves of counters and list
+    // fit 160 KB), 256 with 8-bit ones (their limit is 255), else as many
     // as fit the LDS budget, up to 4096
-    uint32_t mcap = 256;
+    uint32_t mcap = bits == 4 ? 192 : 256;
     if (bits == 16) {
         mcap = 4096;
         while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;
@@ -664,7 +683,11 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         P.lds_ok = 0;
         prof_begin(c, "rz_vote", s, &t);
         const bool shift = P.bs != 0;
-        if (bits == 8 && shift)
+        if (bits == 4 && shift)
+            hipLaunchKernelGGL((k_rz_vote_fast<4, true>), dim3(blocks), dim3(64), fast_lds, s, P);
+        else if (bits == 4)
+            hipLaunchKernelGGL((k_rz_vote_fast<4, false>), dim3(blocks), dim3(64), fast_lds, s, P);
+        else if (bits == 8 && shift)
             hipLaunchKernelGGL((k_rz_vote_fast<8, true>), dim3(blocks), dim3(64), fast_lds, s, P);
         else if (bits == 8)
             hipLaunchKernelGGL((k_rz_vote_fast<8, false>), dim3(blocks), dim3(64), fast_lds, s, P);

@@ -40,7 +40,7 @@ def peak_space():
 
 
 def rz_space():
-    return [dict(rz_waves_per_cu=w, rz_counter_bits=b) for w in (4, 8, 12, 16) for b in (0, 16)]
+    return [dict(rz_waves_per_cu=w, rz_counter_bits=b) for w in (4, 8, 12, 16) for b in (0, 4, 8, 16)]
 
 
 STAGES = (("vote", vote_space), ("peaks", peak_space), ("rz", rz_space))

@@ -289,6 +289,8 @@ def test_peak_and_rz_capacity_overflow(H):
 
 
 @pytest.mark.parametrize("tuning,kw", [
+    (dict(rz_counter_bits=4), {}),
+    (dict(rz_counter_bits=4, rz_waves_per_cu=16), dict(n_phi=4, n_qpt=8, n_cot=70)),  # > 192 members: slow path
     (dict(rz_counter_bits=8), {}),
     (dict(rz_counter_bits=16), {}),
     (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),      # > 255 members: slow path
@@ -302,6 +304,29 @@ def test_rz_kernel_variants(H, tuning, kw):
     tab = oracle.Tables(spec)
     for e in range(batch.n_events):
         check_event(H, tab, res, batch, e, rz=True)
+
+
+@pytest.mark.parametrize("bits", [4, 8, 16])
+def test_rz_counter_overflow_goes_to_exact_path(H, bits):
+    # three identical bin-centre tracks put 30 members into one (cot, z0)
+    # bin of their cell: past a 4-bit counter, which must detect it and
+    # take the exact path; 8- and 16-bit counters hold it directly
+    spec = small_spec()
+    K, N = spec["n_qpt"], spec["n_phi"]
+    kap = spec["qpt_lo"] + (np.arange(K) + 0.5) * (spec["qpt_hi"] - spec["qpt_lo"]) / K
+    layer, phi, z = synth.track_hits(kap[20], (77 + 0.5) / N * 2 * math.pi,
+        cot=-1.2 + 160.5 * 2.4 / 256, z0=-200.0 + 140.5 * 400.0 / 256)
+    rng = np.random.default_rng(9)
+    nl, nphi, nz = (rng.integers(0, 10, 400).astype(np.uint8),
+                    rng.integers(0, 1 << 32, 400, dtype=np.uint64).astype(np.uint32),
+                    rng.integers(-1_200_000, 1_200_000, 400).astype(np.int32))
+    batch = synth.concat_events([(np.concatenate([layer] * 3 + [nl]), np.concatenate([phi] * 3 + [nphi]),
+                                  np.concatenate([z] * 3 + [nz]))])
+    res = run_gpu(H, spec, batch, tuning=dict(rz_counter_bits=bits))
+    tab = oracle.Tables(spec)
+    check_event(H, tab, res, batch, 0, rz=True)
+    grz = H.rz_numpy(res["rz"], res["roff"], 0)
+    assert grz["count"].max() >= 30
 
 
 def test_rz_candidate_cap_selection(H):
