@@ -354,11 +354,17 @@ k_rz_vote_fast(RzParams P)
         const uint32_t k = r.k, p = r.p;
         // all layers' (Z + z0_lo) for this lane's first cot bin, issued now
         // so that they arrive with the member search's loads
+        // Layers >= n_layers are never read except the padding layer 15,
+        // whose value must be 0; the others load a valid row (clamped
+        // index), so every load is unconditional and branch-free.
         const int32_t *zrow = P.Zl + size_t(k) * nl * P.n_cot;
         uint32_t zr[kMaxLayers], zn[kMaxLayers];
+        {
+            const int32_t *zl0 = zrow + min(lane, P.n_cot - 1);
 #pragma unroll
-        for (uint32_t l = 0; l < kMaxLayers; ++l)
-            zr[l] = l < nl ? uint32_t(zrow[size_t(l) * P.n_cot + min(lane, P.n_cot - 1)]) : 0u;
+            for (uint32_t l = 0; l + 1 < kMaxLayers; ++l) zr[l] = uint32_t(zl0[size_t(min(l, nl - 1)) * P.n_cot]);
+            zr[kMaxLayers - 1] = 0u;
+        }
 
         // 1a. lane l < L: the azimuth-bucket window of layer l (one or two
         // ranges of the (layer, bucket)-sorted hits, two when it wraps)
@@ -445,11 +451,12 @@ k_rz_vote_fast(RzParams P)
             for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 64) {
                 const uint32_t j = j0 + lane;
                 const bool jv = j < P.n_cot;
-                const uint32_t jn = min(j + 64, P.n_cot - 1);
-                const bool more = j0 + 64 < P.n_cot;
+                // next pass's rows (after the last pass they are loaded and
+                // not used: the index is clamped, so the loads stay in bounds)
+                const int32_t *zln = zrow + min(j + 64, P.n_cot - 1);
 #pragma unroll
-                for (uint32_t l = 0; l < kMaxLayers; ++l)
-                    zn[l] = (more && l < nl) ? uint32_t(zrow[size_t(l) * P.n_cot + jn]) : 0u;
+                for (uint32_t l = 0; l + 1 < kMaxLayers; ++l) zn[l] = uint32_t(zln[size_t(min(l, nl - 1)) * P.n_cot]);
+                zn[kMaxLayers - 1] = 0u;
                 // all members in one flat loop, eight per step: two 16-byte
                 // LDS reads give eight z, two 4-byte reads their layers (so
                 // (Z + z0_lo) is a register-indexed move).  Per member: the
