@@ -328,10 +328,10 @@ k_rz_vote_fast(RzParams P)
     uint32_t *loff = lay + 96;                       // [L + 1] member offsets per layer
     int32_t *mz = reinterpret_cast<int32_t *>(loff + 32);    // [mcap] member z
     uint8_t *ml = reinterpret_cast<uint8_t *>(mz + P.mcap + 8);  // [mcap + 8] member layer
-    // 8- and 16-bit counters cannot overflow below FIELD members; 4-bit
+    // 16-bit counters cannot overflow below FIELD members; 4- and 8-bit
     // counters detect an overflow instead and send the candidate to the
     // exact slow path
-    const uint32_t lim = BITS == 4 ? P.mcap : min(P.mcap, FIELD);
+    const uint32_t lim = BITS <= 8 ? P.mcap : min(P.mcap, FIELD);
     const uint32_t nb = 1u << P.bucket_bits, bsh = 32 - P.bucket_bits;
     const uint32_t nl = P.n_layers;
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
@@ -444,7 +444,7 @@ k_rz_vote_fast(RzParams P)
         __syncthreads();
 
         uint32_t best_c = 0, best_j = lane, best_b = 0;
-        bool ovf = false;                  // a 4-bit counter of a real bin overflowed
+        bool ovf = false;                  // a 4- or 8-bit counter of a real bin overflowed
         if (nm <= lim) {
             // the next pass's (Z + z0_lo) values are loaded while the current
             // one counts (one memory latency per candidate, not per pass)
@@ -504,7 +504,7 @@ k_rz_vote_fast(RzParams P)
                 const uint32_t bb = uint32_t((fld << 16) - run);
                 // a count of FIELD + 1 can only come from a vote that found
                 // its field full: the counter overflowed
-                if (BITS == 4) ovf = ovf || bc > FIELD;
+                if (BITS <= 8) ovf = ovf || bc > FIELD;
 #pragma unroll
                 for (uint32_t l = 0; l < kMaxLayers; ++l) zr[l] = zn[l];
                 // clear all counters, 16 bytes per lane per store; a store
@@ -518,9 +518,9 @@ k_rz_vote_fast(RzParams P)
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
             }
         }
-        // an overflowed 4-bit count makes every result of this candidate
-        // suspect (a carry reaches the next bin): redo it exactly
-        if (nm > lim || (BITS == 4 && __ballot(ovf) != 0)) {
+        // an overflowed count makes every result of this candidate suspect
+        // (a carry reaches the next bin): redo it exactly
+        if (nm > lim || (BITS <= 8 && __ballot(ovf) != 0)) {
             best_c = 0;
             best_j = lane;
             best_b = 0;
@@ -666,19 +666,22 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     P.fd = make_fastdiv32(P.use32 ? uint32_t(P.span) : 1u);
     P.bm = c->rz_magic_m;
     P.bs = c->rz_magic_s;
-    // counter width: 4 bits (overflow detected, then the slow path) when a
-    // cell's members (about hits / n_phi per event) are few, so that counts
-    // above 15 are rare and 16 waves fit a CU's LDS; 16 bits for dense events
+    // counter width (4- and 8-bit counters detect an overflow and then take
+    // the slow path): 4 bits when a cell's members (about hits / n_phi per
+    // event) are few, so that counts above 15 are rare and 16 waves fit a
+    // CU's LDS; 8 bits for dense events; 16 bits only when tuned so
     const double per_cell = double(h->n_hits) / double(std::max<uint32_t>(E, 1)) / double(g.n_phi);
-    uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 4u : 16u);
+    uint32_t bits = c->tun.rz_counter_bits ? c->tun.rz_counter_bits : (per_cell < 48.0 ? 4u : 8u);
     const uint32_t blocks = c->tun.rz_waves_per_cu ? rz_blocks(c) : uint32_t(c->n_cu) * (bits == 4 ? 16u : 8u);
     // counter dwords per lane: bins 0 .. n_z0 - 1 plus the trash bin n_z0
     const uint32_t hw = g.n_z0 / (32 / bits) + 1;
     // member list: 192 with 4-bit counters (16 waves of counters and list
-    // fit 160 KB), 256 with 8-bit ones (their limit is 255), else as many
-    // as fit the LDS budget, up to 4096
+    // fit 160 KB); otherwise as many as fit the LDS budget, up to 4096: a
+    // candidate with more members takes the slow path, which is far slower
+    // (it walks every hit of the cell's windows per cot bin), so dense
+    // events need the long list more than occupancy
     uint32_t mcap = bits == 4 ? 192 : 256;
-    if (bits == 16) {
+    if (bits != 4) {
         mcap = 4096;
         while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;
     }

@@ -293,7 +293,7 @@ def test_peak_and_rz_capacity_overflow(H):
     (dict(rz_counter_bits=4, rz_waves_per_cu=16), dict(n_phi=4, n_qpt=8, n_cot=70)),  # > 192 members: slow path
     (dict(rz_counter_bits=8), {}),
     (dict(rz_counter_bits=16), {}),
-    (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),      # > 255 members: slow path
+    (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),      # > 512 members: slow path
     (dict(rz_counter_bits=16), dict(n_phi=2, n_qpt=4, n_cot=9)),      # > 1024 members: slow path
     (None, dict(z0_lo_um=-2147483000, z0_hi_um=2147483000, n_z0=64)),  # general kernel
 ])
@@ -306,11 +306,12 @@ def test_rz_kernel_variants(H, tuning, kw):
         check_event(H, tab, res, batch, e, rz=True)
 
 
-@pytest.mark.parametrize("bits", [4, 8, 16])
-def test_rz_counter_overflow_goes_to_exact_path(H, bits):
-    # three identical bin-centre tracks put 30 members into one (cot, z0)
-    # bin of their cell: past a 4-bit counter, which must detect it and
-    # take the exact path; 8- and 16-bit counters hold it directly
+@pytest.mark.parametrize("bits,copies", [(4, 3), (8, 3), (16, 3), (8, 26)])
+def test_rz_counter_overflow_goes_to_exact_path(H, bits, copies):
+    # identical bin-centre tracks put 10 members per copy into one (cot, z0)
+    # bin of their cell: 3 copies pass a 4-bit counter, 26 copies an 8-bit
+    # one, which must detect it and take the exact path; wider counters
+    # hold the count directly
     spec = small_spec()
     K, N = spec["n_qpt"], spec["n_phi"]
     kap = spec["qpt_lo"] + (np.arange(K) + 0.5) * (spec["qpt_hi"] - spec["qpt_lo"]) / K
@@ -320,13 +321,14 @@ def test_rz_counter_overflow_goes_to_exact_path(H, bits):
     nl, nphi, nz = (rng.integers(0, 10, 400).astype(np.uint8),
                     rng.integers(0, 1 << 32, 400, dtype=np.uint64).astype(np.uint32),
                     rng.integers(-1_200_000, 1_200_000, 400).astype(np.int32))
-    batch = synth.concat_events([(np.concatenate([layer] * 3 + [nl]), np.concatenate([phi] * 3 + [nphi]),
-                                  np.concatenate([z] * 3 + [nz]))])
+    batch = synth.concat_events([(np.concatenate([layer] * copies + [nl]),
+                                  np.concatenate([phi] * copies + [nphi]),
+                                  np.concatenate([z] * copies + [nz]))])
     res = run_gpu(H, spec, batch, tuning=dict(rz_counter_bits=bits))
     tab = oracle.Tables(spec)
     check_event(H, tab, res, batch, 0, rz=True)
     grz = H.rz_numpy(res["rz"], res["roff"], 0)
-    assert grz["count"].max() >= 30
+    assert grz["count"].max() >= 10 * copies
 
 
 def test_rz_candidate_cap_selection(H):
