@@ -513,7 +513,9 @@ k_rz_vote_fast(RzParams P)
                 // cot bins are counted
                 __syncthreads();
                 uint4 *h4 = reinterpret_cast<uint4 *>(hist);
-                for (uint32_t i = lane; i < P.hw * 16; i += 64) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+                const uint32_t n4 = P.hw * 16;
+#pragma unroll 4
+                for (uint32_t i = lane; i < n4; i += 64) h4[i] = make_uint4(0u, 0u, 0u, 0u);
                 __syncthreads();
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
             }
