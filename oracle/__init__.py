@@ -61,8 +61,8 @@ def _load():
         lib.orc_rz.restype = C.c_uint64
         lib.orc_clusters.argtypes = [P, C.c_uint64, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_clusters.restype = C.c_uint64
-        lib.orc_fit.argtypes = [P, P, P, C.c_uint64, P, P, C.c_uint64, P, P, P, P,
-                                P, P, P, P, P, P, P]
+        lib.orc_fit.argtypes = [P, P, P, C.c_uint64, P, P, P, C.c_uint64, P, P, P, P,
+                                P, P, P, P, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -240,26 +240,30 @@ def cluster_centroids(tab, pk, cl):
 
 
 FIT_DTYPE = np.dtype([("qpt", np.float64), ("phi0", np.float64), ("qpt_c", np.float64),
-                      ("phi0_c", np.float64), ("rms_mm", np.float64), ("n_hits", np.uint32),
-                      ("status", np.uint32)])
+                      ("phi0_c", np.float64), ("rms_mm", np.float64), ("cot", np.float64),
+                      ("z0_mm", np.float64), ("rms_z_mm", np.float64), ("n_hits", np.uint32),
+                      ("status", np.uint32), ("status_z", np.uint32)])
 
 
-def fit(tab, layer, phi, pk, cl):
-    """Track fit of each cluster of one event over the hits that voted into
-    its first peak cell (beam-line grids only), plus its centroid
-    parameters; FIT_DTYPE records in cluster order."""
+def fit(tab, layer, phi, pk, cl, z=None):
+    """Helix fit of each cluster of one event over the hits that voted into
+    its first peak cell (beam-line grids only): the transverse circle, and,
+    when z is given, the line z = z0 + cot s; plus the centroid parameters.
+    FIT_DTYPE records in cluster order."""
     if tab.spec["n_d0"] != 1:
         raise ValueError("the cluster fit needs a grid without a d0 axis")
-    layer, phi, _ = _hits(layer, phi)
+    layer, phi, z = _hits(layer, phi, z)
     n = len(cl)
     first = np.ascontiguousarray(pk["cell"][cl["first"]], np.uint32)
     npk = np.ascontiguousarray(cl["n_peaks"], np.uint32)
     sdk = np.ascontiguousarray(cl["sum_dk"], np.int32)
     sdp = np.ascontiguousarray(cl["sum_dp"], np.int32)
-    d = [np.zeros(n + 1) for _ in range(5)]
-    u = [np.zeros(n + 1, np.uint32) for _ in range(2)]
-    _load().orc_fit(C.byref(tab.cs), _p(tab.O), _p(tab.V), len(layer), _p(layer), _p(phi), n,
-                    _p(first), _p(npk), _p(sdk), _p(sdp), *[_p(x) for x in d], *[_p(x) for x in u])
+    d = [np.zeros(n + 1) for _ in range(8)]
+    u = [np.zeros(n + 1, np.uint32) for _ in range(3)]
+    _load().orc_fit(C.byref(tab.cs), _p(tab.O), _p(tab.V), len(layer), _p(layer), _p(phi),
+                    None if z is None else _p(z), n,
+                    _p(first), _p(npk), _p(sdk), _p(sdp), *[_p(x) for x in d[:5]], *[_p(x) for x in d[5:]],
+                    *[_p(x) for x in u])
     out = np.zeros(n, FIT_DTYPE)
     for name, x in zip(FIT_DTYPE.names, d + u):
         out[name] = x[:n]

@@ -463,12 +463,26 @@ uint64_t orc_clusters(const orc_spec *g, uint64_t n, const uint32_t *cell, const
  * zero fit outputs.  The centroid parameters are the bin-centre formulas
  * evaluated at the centroid: q/pT_c = qpt_lo + (k_c + 1/2) (qpt_hi - qpt_lo)
  * / n_qpt, phi0_c = 2 pi ((p_c + 1/2) / n_phi mod 1). */
+/* Longitudinal part (when z is given, z != NULL, and the transverse fit
+ * succeeded): a member at radius r lies at z = z0 + cot(theta) s, s the
+ * transverse arc length from the perigee along the fitted circle,
+ * s = (2 / rho) asin(rho r / 2) (s = r for rho = 0).  (z0, cot) is the
+ * least-squares line through the members' (s, z) points (z in mm), from
+ * [M  Ss; Ss  Sss] [z0; cot] = [Sz; Ssz]; status_z = 1 when det =
+ * M Sss - Ss^2 > 1e-12 M Sss, and rms_z_mm is the rms of z - z0 - cot s. */
+static double arc_length(double rho, double r)
+{
+    double x = 0.5 * rho * r;
+    return x == 0.0 ? r : r * (asin(x) / x);
+}
+
 void orc_fit(const orc_spec *g, const uint32_t *O, const uint8_t *V,
-             uint64_t n_hits, const uint8_t *layer, const uint32_t *phi,
+             uint64_t n_hits, const uint8_t *layer, const uint32_t *phi, const int32_t *z,
              uint64_t n_clusters, const uint32_t *first_cell, const uint32_t *n_peaks,
              const int32_t *sum_dk, const int32_t *sum_dp,
              double *qpt, double *phi0, double *qpt_c, double *phi0_c, double *rms,
-             uint32_t *n_fit, uint32_t *status)
+             double *cot, double *z0_mm, double *rms_z,
+             uint32_t *n_fit, uint32_t *status, uint32_t *status_z)
 {
     const double two_pi = 2.0 * M_PI;
     const double turn_rad = two_pi / 4294967296.0;
@@ -523,9 +537,44 @@ void orc_fit(const orc_spec *g, const uint32_t *O, const uint8_t *V,
             }
         }
         n_fit[c] = m;
+        cot[c] = z0_mm[c] = rms_z[c] = 0.0;
+        status_z[c] = 0;
         if (m < 3 || !(sxx * sww - sxw * sxw > 1e-12 * sxx * sww)) {
             qpt[c] = phi0[c] = rms[c] = 0.0;
             status[c] = 0;
+            continue;
+        }
+        if (!z) continue;
+        /* longitudinal line over the same members */
+        double rho = qpt[c] * 0.299792458e-3 * g->b_tesla;
+        double s1 = 0, s2 = 0, sz = 0, ssz = 0;
+        double zz0 = 0, zcot = 0, zss = 0;
+        for (int pass = 0; pass < 2; pass++) {
+            for (uint64_t h = 0; h < n_hits; h++) {
+                uint32_t l = layer[h];
+                if (l >= g->n_layers) continue;
+                size_t ti = (size_t)l * g->n_qpt + k;
+                if (!V[ti] || ((uint32_t)(phi[h] - O[ti]) >> s) != p) continue;
+                double sa = arc_length(rho, g->layer_r_mm[l]);
+                double zm = (double)z[h] * 1e-3;
+                if (pass == 0) {
+                    s1 += sa; s2 += sa * sa; sz += zm; ssz += sa * zm;
+                } else {
+                    double res = zm - zz0 - zcot * sa;
+                    zss += res * res;
+                }
+            }
+            if (pass == 0) {
+                double det = (double)m * s2 - s1 * s1;
+                if (!(det > 1e-12 * (double)m * s2)) break;
+                zz0 = (s2 * sz - s1 * ssz) / det;
+                zcot = ((double)m * ssz - s1 * sz) / det;
+            } else {
+                cot[c] = zcot;
+                z0_mm[c] = zz0;
+                rms_z[c] = sqrt(zss / m);
+                status_z[c] = 1;
+            }
         }
     }
 }

@@ -790,3 +790,55 @@ def test_fit_centroid_and_degenerate_clusters():
     assert g["status"].tolist() == [0, 0]
     assert np.all(g["qpt"] == 0) and np.all(g["rms_mm"] == 0)
     assert g["qpt_c"][1] == pytest.approx(kap[9], abs=1e-12)
+
+
+@pytest.mark.parametrize("qpt,phi0,cot,z0", [(0.3131, 1.234, 0.7, 23.4), (-0.8765, 4.5678, -1.1, -80.0),
+                                             (0.0217, 0.0004, 0.05, 1.5), (0.6, 6.0, 0.0, 0.0)])
+def test_helix_fit_recovers_generator_cot_and_z0(qpt, phi0, cot, z0):
+    # noiseless generator helices (z quantised to 1 um): the line through
+    # (arc length, z) of the members gives back cot(theta) and z0
+    spec = synth.grid_spec("c2_single_1ktrk_rz")
+    tab = oracle.Tables(spec)
+    layer, phi, z = synth.track_hits(qpt, phi0, cot=cot, z0=z0)
+    pk, cl = _clusters_of(tab, layer, phi)
+    f = oracle.fit(tab, layer, phi, pk, cl, z)
+    g = f[f["status_z"] == 1]
+    assert len(g) == np.count_nonzero(f["status"]) >= 1
+    assert np.all(np.abs(g["cot"] - cot) < 5e-6)
+    assert np.all(np.abs(g["z0_mm"] - z0) < 1e-3)
+    assert np.all(g["rms_z_mm"] < 1e-3)
+    # without z only the transverse part is fitted
+    h = oracle.fit(tab, layer, phi, pk, cl)
+    assert np.all(h["status_z"] == 0) and np.all(h["cot"] == 0)
+    np.testing.assert_array_equal(h["qpt"], f["qpt"])
+
+
+def test_helix_fit_line_matches_lstsq():
+    spec = synth.grid_spec("c2_single_1ktrk_rz")
+    tab = oracle.Tables(spec)
+    rng = np.random.default_rng(31)
+    layer, phi, z = synth.track_hits(rng.uniform(-0.9, 0.9, 30), rng.uniform(0, 2 * math.pi, 30),
+                                     cot=rng.uniform(-1, 1, 30), z0=rng.normal(0, 50, 30), rng=rng)
+    nl, nphi, nz = random_hits(rng, 20000)
+    layer, phi, z = (np.concatenate([layer, nl]), np.concatenate([phi, nphi]), np.concatenate([z, nz]))
+    pk, cl = _clusters_of(tab, layer, phi)
+    f = oracle.fit(tab, layer, phi, pk, cl, z)
+    s = 32 - 10
+    R = np.asarray(spec["layer_r_mm"][:spec["n_layers"]])
+    C = 0.299792458e-3 * spec["b_tesla"]
+    checked = 0
+    for c in np.flatnonzero(f["status_z"] == 1)[:200]:
+        cell = int(pk["cell"][cl["first"][c]])
+        k, p = cell // 1024, cell % 1024
+        mem = np.array([h for h in range(len(layer)) if tab.V[layer[h], 0, k]
+                        and ((int(phi[h]) - int(tab.O[layer[h], 0, k])) % (1 << 32)) >> s == p])
+        r = R[layer[mem]]
+        x = 0.5 * f["qpt"][c] * C * r
+        sa = np.where(x == 0, r, r * np.arcsin(x) / np.where(x == 0, 1, x))
+        sol, *_ = np.linalg.lstsq(np.stack([np.ones_like(sa), sa], 1), z[mem] * 1e-3, rcond=None)
+        assert f["z0_mm"][c] == pytest.approx(sol[0], rel=1e-7, abs=1e-7)
+        assert f["cot"][c] == pytest.approx(sol[1], rel=1e-7, abs=1e-9)
+        res = z[mem] * 1e-3 - sol[0] - sol[1] * sa
+        assert f["rms_z_mm"][c] == pytest.approx(math.sqrt(np.mean(res ** 2)), rel=1e-6, abs=1e-9)
+        checked += 1
+    assert checked >= 20
