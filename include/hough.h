@@ -145,15 +145,20 @@ typedef struct {
     int32_t  sum_dd;                /* sum over members of d - d_f */
 } hough_cluster;
 
-/* Track fit of one plateau cluster (hough_cluster_fit).  48 bytes. */
+/* Helix fit of one plateau cluster (hough_cluster_fit).  80 bytes. */
 typedef struct {
     double   qpt;                   /* fitted q/pT, 1/GeV (0 when status == 0) */
     double   phi0;                  /* fitted phi0, radians in [0, 2 pi) (0 when status == 0) */
     double   qpt_c;                 /* q/pT at the cluster centroid (bin-centre formula) */
     double   phi0_c;                /* phi0 at the cluster centroid, radians in [0, 2 pi) */
     double   rms_mm;                /* rms residual of the members, mm (0 when status == 0) */
+    double   cot;                   /* fitted cot(theta) (0 when status_z == 0) */
+    double   z0_mm;                 /* fitted z0, mm (0 when status_z == 0) */
+    double   rms_z_mm;              /* rms of the members' z residuals, mm (0 when status_z == 0) */
     uint32_t n_hits;                /* members: hits that voted into the first peak's cell */
     uint32_t status;                /* 1 = fitted; 0 = fewer than 3 members or singular */
+    uint32_t status_z;              /* 1 = line fitted (grids with an rz stage, z given) */
+    uint32_t reserved;
 } hough_fit;
 
 /* Autotuning knobs of the kernels (all 0 = library default). */
@@ -252,7 +257,7 @@ int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_c
                         hough_cluster *clusters, uint64_t capacity, uint64_t *event_cluster_offsets,
                         void *stream);
 
-/* Candidate confirmation, track fit (grids without a d0 axis; HOUGH_EINVAL
+/* Candidate confirmation, helix fit (grids without a d0 axis; HOUGH_EINVAL
  * when n_d0 > 1).  On such a grid a hit (r, phi) lies on the track (q/pT,
  * phi0) when y cos phi0 - x sin phi0 + rho r^2 / 2 = 0, x = r cos phi,
  * y = r sin phi, rho = 0.299792458e-3 B q/pT (the track model of the vote's
@@ -263,7 +268,12 @@ int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_c
  * alpha = rho / (2 cos(phi0 - phi_ref)), and (t, alpha) is the least-squares
  * solution over the members (normal equations, Cramer's rule; status 1 when
  * there are >= 3 members and det > 1e-12 Sxx Sww).  rms_mm is the rms of
- * (y' - t x' + alpha r^2) cos(phi0 - phi_ref) over the members.  qpt_c and
+ * (y' - t x' + alpha r^2) cos(phi0 - phi_ref) over the members.  On a grid
+ * with an rz stage, when hits->z_um is set and the circle is fitted, the
+ * members' (s, z) with s = (2 / rho) asin(rho r / 2) (s = r for rho = 0),
+ * the transverse arc length along the fitted circle, give the least-squares
+ * line z = z0 + cot s (status_z 1 when det = M Sss - Ss^2 > 1e-12 M Sss;
+ * rms_z_mm the rms of its residuals): with the circle, the helix.  qpt_c and
  * phi0_c evaluate the bin-centre formulas at the centroid.  Records go to
  * out[c] (device, `capacity` records, 8-byte aligned).  hits are the hits
  * the peaks were found from (same n_events); peaks/event_peak_offsets are

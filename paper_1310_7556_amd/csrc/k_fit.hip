@@ -14,7 +14,11 @@
 // cluster: pass 1 sums x'^2, x' r^2, r^4, x' y', y' r^2 over the members,
 // found in the few azimuth buckets per layer that cover the cell (hits
 // sorted by (layer, bucket) per event), pass 2 the squared residuals of the
-// solution; fp64 throughout, wave sums by a fixed butterfly.
+// solution.  With z (grids with an rz stage), the residual pass also sums
+// the members' (arc length, z) and a third pass takes the residuals of the
+// least-squares line z = z0 + cot(theta) s, s the transverse arc length
+// (2 / rho) asin(rho r / 2) along the fitted circle: the helix.  fp64
+// throughout, wave sums by a fixed butterfly.
 #include "hough_internal.h"
 
 namespace hough {
@@ -22,6 +26,7 @@ namespace {
 
 struct FitParams {
     const uint32_t *phi_b;        // hits grouped by (layer, azimuth bucket) per event
+    const int32_t *z_b;           // their z (um), or null: no longitudinal fit
     const uint32_t *bucket_off;   // [E][L][NB + 1] relative to the event start
     uint32_t bucket_bits;
     const uint64_t *hoff;         // [E + 1] hit offsets
@@ -116,11 +121,14 @@ __device__ __forceinline__ void for_members(const FitParams &P, const Windows &w
         if (gi < w.total) {
             const uint32_t h = local < l1 ? h1 + local : h2 + (local - l1);
             const uint32_t ph = P.phi_b[eb + h];
-            if (((ph - o) >> P.shift) == p) visit(ls, ph);
+            if (((ph - o) >> P.shift) == p) visit(ls, ph, h);
         }
     }
 }
 
+// Z: the longitudinal line is fitted too (P.z_b set); a separate instance
+// keeps the transverse-only kernel's register count (and occupancy) down.
+template <bool Z>
 __global__ void __launch_bounds__(256) k_fit(FitParams P)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -159,7 +167,7 @@ __global__ void __launch_bounds__(256) k_fit(FitParams P)
             const Windows w = layer_windows(P, e, k, p, lane);
             double sxx = 0, sxw = 0, sww = 0, sxy = 0, syw = 0;
             uint32_t m = 0;
-            for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t ph) {
+            for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t ph, uint32_t) {
                 double sa, ca;
                 sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
                 const double r = P.r_mm[l], wr = r * r;
@@ -183,19 +191,55 @@ __global__ void __launch_bounds__(256) k_fit(FitParams P)
                 const double t = (sxy * sww - sxw * syw) / det;
                 const double alpha = (sxw * sxy - sxx * syw) / det;
                 const double cosp = 1.0 / sqrt(1.0 + t * t);
-                double ss = 0;
-                for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t ph) {
+                const double qpt = 2.0 * alpha * cosp * P.inv_curv;
+                const double rho = qpt / P.inv_curv;
+                // arc length from the perigee along the fitted circle
+                auto arc = [&](double r) {
+                    const double x = 0.5 * rho * r;
+                    return x == 0.0 ? r : r * (asin(x) / x);
+                };
+                double ss = 0, s1 = 0, s2 = 0, sz = 0, ssz = 0;
+                for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t ph, uint32_t h) {
                     double sa, ca;
                     sincos(double(int32_t(ph - ref)) * turn_rad, &sa, &ca);
                     const double r = P.r_mm[l];
                     const double res = (r * sa - t * (r * ca) + alpha * (r * r)) * cosp;
                     ss += res * res;
+                    if (Z) {
+                        const double s = arc(r), zm = double(P.z_b[eb + h]) * 1e-3;
+                        s1 += s;
+                        s2 += s * s;
+                        sz += zm;
+                        ssz += s * zm;
+                    }
                 });
                 ss = wave_sum(ss);
+                if (Z) {
+                    s1 = wave_sum(s1);
+                    s2 = wave_sum(s2);
+                    sz = wave_sum(sz);
+                    ssz = wave_sum(ssz);
+                    // the line z = z0 + cot s through the members
+                    const double dm = double(m), detz = dm * s2 - s1 * s1;
+                    if (detz > 1e-12 * dm * s2) {
+                        const double z0 = (s2 * sz - s1 * ssz) / detz;
+                        const double ct = (dm * ssz - s1 * sz) / detz;
+                        double sr = 0;
+                        for_members(P, w, eb, p, lane, [&](uint32_t l, uint32_t, uint32_t h) {
+                            const double res = double(P.z_b[eb + h]) * 1e-3 - z0 - ct * arc(P.r_mm[l]);
+                            sr += res * res;
+                        });
+                        sr = wave_sum(sr);
+                        f.cot = ct;
+                        f.z0_mm = z0;
+                        f.rms_z_mm = sqrt(sr / m);
+                        f.status_z = 1;
+                    }
+                }
                 double ph0 = fmod(double(ref) * turn_rad + atan(t), two_pi);
                 if (ph0 < 0) ph0 += two_pi;
                 f.phi0 = ph0;
-                f.qpt = 2.0 * alpha * cosp * P.inv_curv;
+                f.qpt = qpt;
                 f.rms_mm = sqrt(ss / m);
                 f.status = 1;
             }
@@ -211,11 +255,14 @@ hipError_t launch_fit(hough_ctx *c, const hough_hits *h, const hough_peak *peaks
                       hough_fit *out, hipStream_t s)
 {
     if (h->n_events == 0 || capacity == 0) return hipSuccess;
-    hipError_t err = launch_bucket_layers(c, h, false, s);
-    if (err == hipSuccess) err = launch_bucket_phi(c, h, s, false);
+    // the longitudinal line needs z, bucketed with the azimuths (rz grids)
+    const bool with_z = c->spec.n_z0 > 0 && h->z_um != nullptr;
+    hipError_t err = launch_bucket_layers(c, h, with_z, s);
+    if (err == hipSuccess) err = launch_bucket_phi(c, h, s, with_z);
     if (err != hipSuccess) return err;
     FitParams P{};
     P.phi_b = c->d_phi_b;
+    P.z_b = with_z ? c->d_z_b : nullptr;
     P.bucket_off = c->d_bucket_off;
     P.bucket_bits = c->bucket_bits;
     P.hoff = h->event_offsets;
@@ -242,7 +289,10 @@ hipError_t launch_fit(hough_ctx *c, const hough_hits *h, const hough_peak *peaks
     const uint64_t blocks = std::min<uint64_t>((capacity + 3) / 4, uint64_t(c->n_cu) * 16);
     KernelTimer t;
     prof_begin(c, "cluster_fit", s, &t);
-    hipLaunchKernelGGL(k_fit, dim3(uint32_t(std::max<uint64_t>(blocks, 1))), dim3(256), 0, s, P);
+    if (with_z)
+        hipLaunchKernelGGL(k_fit<true>, dim3(uint32_t(std::max<uint64_t>(blocks, 1))), dim3(256), 0, s, P);
+    else
+        hipLaunchKernelGGL(k_fit<false>, dim3(uint32_t(std::max<uint64_t>(blocks, 1))), dim3(256), 0, s, P);
     prof_end(c, s, &t);
     return hipGetLastError();
 }

@@ -34,8 +34,9 @@ CLUSTER_DTYPE = np.dtype([("first", np.uint32), ("popcount", np.uint16), ("mask_
                           ("n_peaks", np.uint32), ("sum_dk", np.int32), ("sum_dp", np.int32),
                           ("sum_dd", np.int32)])
 FIT_DTYPE = np.dtype([("qpt", np.float64), ("phi0", np.float64), ("qpt_c", np.float64),
-                      ("phi0_c", np.float64), ("rms_mm", np.float64), ("n_hits", np.uint32),
-                      ("status", np.uint32)])
+                      ("phi0_c", np.float64), ("rms_mm", np.float64), ("cot", np.float64),
+                      ("z0_mm", np.float64), ("rms_z_mm", np.float64), ("n_hits", np.uint32),
+                      ("status", np.uint32), ("status_z", np.uint32), ("reserved", np.uint32)])
 
 
 class GridSpec(C.Structure):
@@ -369,13 +370,13 @@ class HoughContext:
         return labels, out, offsets
 
     def new_fits(self, capacity):
-        """Fit records: float64 tensor of 6 words each."""
+        """Fit records: float64 tensor of 10 words (80 bytes) each."""
         torch = _torch()
-        return torch.empty((max(capacity, 1), 6), dtype=torch.float64, device=f"cuda:{self.device}")
+        return torch.empty((max(capacity, 1), 10), dtype=torch.float64, device=f"cuda:{self.device}")
 
     def cluster_fit(self, hits, peaks, peak_offsets, clusters, cluster_offsets, peak_capacity=None,
                     capacity=None, out=None, stream=None):
-        """Track fit of every stored cluster (grids without a d0 axis)."""
+        """Helix fit of every stored cluster (grids without a d0 axis)."""
         if peak_capacity is None:
             peak_capacity = peaks.shape[0]
         if capacity is None:

@@ -246,7 +246,8 @@ WORST = {}
 def check_fit(H, got, want, what=""):
     np.testing.assert_array_equal(got["n_hits"], want["n_hits"], err_msg=f"n_hits {what}")
     np.testing.assert_array_equal(got["status"], want["status"], err_msg=f"status {what}")
-    for f in ("qpt", "phi0", "qpt_c", "phi0_c", "rms_mm"):
+    np.testing.assert_array_equal(got["status_z"], want["status_z"], err_msg=f"status_z {what}")
+    for f in ("qpt", "phi0", "qpt_c", "phi0_c", "rms_mm", "cot", "z0_mm", "rms_z_mm"):
         d = np.abs(got[f] - want[f])
         if f.startswith("phi0"):
             d = np.minimum(d, 2 * np.pi - d)            # the same angle across the wrap
@@ -273,7 +274,7 @@ def run_fit(H, name, batch, events=None, cl_cap=None):
         ev = batch.event(e)
         opk = oracle.peaks(tab, oracle.vote_mask(tab, ev.layer, ev.phi))
         _, ocl = oracle.clusters(tab, opk)
-        want = oracle.fit(tab, ev.layer, ev.phi, opk, ocl)
+        want = oracle.fit(tab, ev.layer, ev.phi, opk, ocl, ev.z if spec["n_z0"] else None)
         lo, hi = min(int(gco[e]), cl_cap), min(int(gco[e + 1]), cl_cap)
         got = fits[lo:hi].cpu().numpy().view(H.FIT_DTYPE).reshape(-1)
         check_fit(H, got, want[:hi - lo], what=f"event {e}")
@@ -289,6 +290,7 @@ def test_fit_c2_full(H):
     fits, coff = run_fit(H, name, synth.gen_config(name))
     f = H.fits_numpy(fits, coff)
     assert np.count_nonzero(f["status"]) > len(f) // 2
+    assert np.count_nonzero(f["status_z"]) > len(f) // 2          # the rz grid fits the helix
 
 
 def test_fit_c4_sampled_events_and_cluster_capacity(H):
@@ -300,19 +302,21 @@ def test_fit_c4_sampled_events_and_cluster_capacity(H):
 
 
 def test_fit_generator_tracks_recover_truth(H):
-    # noiseless tracks off the bin centres: the device fit lands on the
-    # generator's parameters, as the oracle's does
+    # noiseless helices off the bin centres: the device fit lands on the
+    # generator's parameters (cot 0.4, z0 12.5 mm), as the oracle's does
     name = "c2_single_1ktrk_rz"
     spec = synth.grid_spec(name)
     truth = [(0.3131, 1.234), (-0.8765, 4.5678), (0.0217, 0.0004), (-0.5, 2 * np.pi - 0.0007)]
     from synth.events import concat_events
-    batch = concat_events([synth.track_hits(q, p) for q, p in truth])
+    batch = concat_events([synth.track_hits(q, p, cot=0.4, z0=12.5) for q, p in truth])
     fits, coff = run_fit(H, name, batch)
     for e, (q, p) in enumerate(truth):
         f = H.fits_numpy(fits, coff, e)
         good = f[f["status"] == 1]
         assert len(good) and np.all(np.abs(good["qpt"] - q) < 2e-6)
         assert np.all(np.abs(np.angle(np.exp(1j * (good["phi0"] - p)))) < 1e-7)
+        assert np.all(good["status_z"] == 1)
+        assert np.all(np.abs(good["cot"] - 0.4) < 5e-6) and np.all(np.abs(good["z0_mm"] - 12.5) < 1e-3)
 
 
 def test_fit_rejects_d0_grid_and_reports_worst_difference(H):
