@@ -179,20 +179,39 @@ k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uin
     const uint32_t lv = log2phi - 3;
     const uint32_t nvec = planes * prow * vpr;
     const uint32_t cp = planes == 3 ? 1 : 0;
-    for (uint32_t i = t; i < nvec; i += nt) {
-        const uint32_t ri = i >> lv, col = i & (vpr - 1);
-        const uint32_t pl = planes == 1 ? 0 : (ri >= 2 * prow ? 2 : ri >= prow ? 1 : 0);
-        const uint32_t rr = ri - pl * prow;
-        const int dd = planes == 3 ? int(d) + int(pl) - 1 : int(d);
-        const int kk = int(k0) + int(rr) - 1;
-        uint4 packed = make_uint4(0u, 0u, 0u, 0u);
-        if (dd >= 0 && dd < int(n_d0) && kk >= 0 && kk < int(n_qpt)) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(ev + (uint64_t(dd) * n_qpt + kk) * nphi + col * 8);
-            packed = make_uint4(popc2(v.x), popc2(v.y), popc2(v.z), popc2(v.w));
-            if (WRITE && pl == cp && rr >= 1 && rr <= nr)
-                *reinterpret_cast<uint4 *>(raw + (rr - 1) * nphi + col * 8) = v;
+    // staging, four vectors per thread per step: all four loads are issued
+    // before any is used, so a tile pays the memory latency once per step
+    constexpr uint32_t kStageU = 4;
+    for (uint32_t i0 = t; i0 < nvec; i0 += kStageU * nt) {
+        uint4 v[kStageU];
+        bool ok[kStageU];
+#pragma unroll
+        for (uint32_t u = 0; u < kStageU; ++u) {
+            const uint32_t i = i0 + u * nt;
+            const uint32_t ri = i >> lv, col = i & (vpr - 1);
+            const uint32_t pl = planes == 1 ? 0 : (ri >= 2 * prow ? 2 : ri >= prow ? 1 : 0);
+            const uint32_t rr = ri - pl * prow;
+            const int dd = planes == 3 ? int(d) + int(pl) - 1 : int(d);
+            const int kk = int(k0) + int(rr) - 1;
+            ok[u] = i < nvec && dd >= 0 && dd < int(n_d0) && kk >= 0 && kk < int(n_qpt);
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (ok[u]) v[u] = *reinterpret_cast<const uint4 *>(ev + (uint64_t(dd) * n_qpt + kk) * nphi + col * 8);
         }
-        *reinterpret_cast<uint4 *>(pc + size_t(ri) * nphi + col * 8) = packed;
+#pragma unroll
+        for (uint32_t u = 0; u < kStageU; ++u) {
+            const uint32_t i = i0 + u * nt;
+            if (i >= nvec) break;
+            const uint32_t ri = i >> lv, col = i & (vpr - 1);
+            const uint32_t pl = planes == 1 ? 0 : (ri >= 2 * prow ? 2 : ri >= prow ? 1 : 0);
+            const uint32_t rr = ri - pl * prow;
+            uint4 packed = make_uint4(0u, 0u, 0u, 0u);
+            if (ok[u]) {
+                packed = make_uint4(popc2(v[u].x), popc2(v[u].y), popc2(v[u].z), popc2(v[u].w));
+                if (WRITE && pl == cp && rr >= 1 && rr <= nr)
+                    *reinterpret_cast<uint4 *>(raw + (rr - 1) * nphi + col * 8) = v[u];
+            }
+            *reinterpret_cast<uint4 *>(pc + size_t(ri) * nphi + col * 8) = packed;
+        }
     }
     __syncthreads();
 
