@@ -172,8 +172,6 @@ typedef struct {
                                        3 = hit-gap lists, 4 = bucket bounds (direct occupancy) */
     uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
     uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 4, 8 or 16 */
-    uint32_t peak_one_pass;         /* 1: one pass with a look-back scan where the vector kernel
-                                       applies; 0 (default): count pass, scan, write pass */
 } hough_tuning;
 
 /* ---- context --------------------------------------------------------- */

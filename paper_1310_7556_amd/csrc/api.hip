@@ -88,7 +88,6 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 4 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16)
         return false;
-    if (t.peak_one_pass > 1) return false;
     return true;
 }
 

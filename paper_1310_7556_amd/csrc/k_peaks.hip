@@ -300,204 +300,6 @@ k_peaks_vec(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uin
     }
 }
 
-// Single-pass form of k_peaks_vec<true>: persistent workgroups take tiles
-// in ticket order; each counts its tile's peaks, publishes the count,
-// looks back over its predecessors' published values for its offset
-// (64 at a time, one per lane of wave 0, stopping at the nearest that
-// carries an inclusive prefix), publishes its own inclusive prefix, and
-// then writes its records as k_peaks_vec<true> does.  A tile only ever waits for tiles with smaller tickets, which
-// belong to running workgroups that publish their count before they wait
-// for anything, so the wait always ends; it is bounded all the same (a
-// workgroup that gives up counts the event in *err and carries on).
-// status[tile] = flag << 62 | value, flag 1 = tile count, 2 = inclusive
-// prefix; status and the ticket start at 0.
-constexpr uint32_t kLookbackSpins = 1u << 22;
-
-__global__ void __launch_bounds__(256)
-k_peaks_one(const uint16_t *__restrict__ acc, uint32_t n_d0, uint32_t n_qpt, uint32_t nphi, uint32_t log2phi,
-            uint32_t rp, uint32_t n_kt, uint32_t thr, uint32_t n_items, uint32_t *__restrict__ ticket,
-            uint64_t *__restrict__ status, uint32_t *__restrict__ err, uint64_t *__restrict__ event_off,
-            hough_peak *__restrict__ peaks, uint64_t capacity)
-{
-    HOUGH_DYNAMIC_LDS(uint4, lds4);
-    __shared__ uint32_t wave_cnt[4];
-    __shared__ uint32_t s_item;
-    __shared__ uint64_t s_base;
-    const uint32_t t = threadIdx.x, nt = blockDim.x;    // nt == 256
-    const uint32_t lane = t & 63, wave = t >> 6, nwaves = nt >> 6;
-    const uint32_t per_event = n_d0 * n_kt;
-    const uint32_t planes = n_d0 > 1 ? 3 : 1;
-    const uint64_t cells = uint64_t(n_d0) * n_qpt * nphi;
-    const uint32_t vpr = nphi >> 3, lv = log2phi - 3;
-    const uint32_t cp = planes == 3 ? 1 : 0;
-    const uint32_t t2 = min(thr, 17u) * 0x00010001u;    // popcounts are <= 16
-    constexpr uint64_t kVal = (uint64_t(1) << 62) - 1;
-    for (;;) {
-        if (t == 0) s_item = atomicAdd(ticket, 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
-        if (item >= n_items) break;
-        const uint32_t e = item / per_event;
-        const uint32_t d = (item % per_event) / n_kt;
-        const uint32_t k0 = (item % n_kt) * rp;
-        const uint32_t nr = min(rp, n_qpt - k0);
-        const uint32_t prow = nr + 2;
-        const uint16_t *ev = acc + uint64_t(e) * cells;
-        uint16_t *pc = reinterpret_cast<uint16_t *>(lds4);
-        const size_t pc_bytes = (size_t(planes) * prow * nphi * 2 + 15) & ~size_t(15);
-        uint16_t *raw = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lds4) + pc_bytes);
-        uint2 *rec = reinterpret_cast<uint2 *>(reinterpret_cast<char *>(raw) + size_t(nr) * nphi * 2);
-
-        const uint32_t nvec = planes * prow * vpr;
-        for (uint32_t i = t; i < nvec; i += nt) {
-            const uint32_t ri = i >> lv, col = i & (vpr - 1);
-            const uint32_t pl = planes == 1 ? 0 : (ri >= 2 * prow ? 2 : ri >= prow ? 1 : 0);
-            const uint32_t rr = ri - pl * prow;
-            const int dd = planes == 3 ? int(d) + int(pl) - 1 : int(d);
-            const int kk = int(k0) + int(rr) - 1;
-            uint4 packed = make_uint4(0u, 0u, 0u, 0u);
-            if (dd >= 0 && dd < int(n_d0) && kk >= 0 && kk < int(n_qpt)) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(ev + (uint64_t(dd) * n_qpt + kk) * nphi + col * 8);
-                packed = make_uint4(popc2(v.x), popc2(v.y), popc2(v.z), popc2(v.w));
-                if (pl == cp && rr >= 1 && rr <= nr)
-                    *reinterpret_cast<uint4 *>(raw + (rr - 1) * nphi + col * 8) = v;
-            }
-            *reinterpret_cast<uint4 *>(pc + size_t(ri) * nphi + col * 8) = packed;
-        }
-        __syncthreads();
-
-        // peak flags of the 4 cells of quad q (as in k_peaks_vec)
-        const uint32_t nquad = (nr * nphi) >> 2;
-        auto quad_bits = [&](uint32_t q) -> uint32_t {
-            const uint32_t rr = (q << 2) >> log2phi;
-            const uint32_t p0 = (q << 2) & (nphi - 1);
-            const uint32_t pm = (p0 - 2) & (nphi - 1), pn = (p0 + 4) & (nphi - 1);
-            const uint2 vv = *reinterpret_cast<const uint2 *>(pc + (cp * prow + rr + 1) * nphi + p0);
-            uint32_t m0 = t2, m1 = t2;
-            for (uint32_t pl = 0; pl < planes; ++pl) {
-#pragma unroll
-                for (uint32_t dr = 0; dr < 3; ++dr) {
-                    const uint16_t *row = pc + (pl * prow + rr + dr) * nphi;
-                    const uint2 w = *reinterpret_cast<const uint2 *>(row + p0);
-                    const uint32_t wl = *reinterpret_cast<const uint32_t *>(row + pm);
-                    const uint32_t wr = *reinterpret_cast<const uint32_t *>(row + pn);
-                    const uint32_t mid = shift_pair(w.y, w.x);
-                    m0 = pk_max_u16(m0, pk_max_u16(shift_pair(w.x, wl), mid));
-                    m1 = pk_max_u16(m1, pk_max_u16(mid, shift_pair(wr, w.y)));
-                    if (!(pl == cp && dr == 1)) {
-                        m0 = pk_max_u16(m0, w.x);
-                        m1 = pk_max_u16(m1, w.y);
-                    }
-                }
-            }
-            const uint32_t x0 = pk_max_u16(m0, vv.x) ^ vv.x, x1 = pk_max_u16(m1, vv.y) ^ vv.y;
-            return ((x0 & 0xFFFFu) == 0 ? 1u : 0u) | ((x0 >> 16) == 0 ? 2u : 0u) |
-                   ((x1 & 0xFFFFu) == 0 ? 4u : 0u) | ((x1 >> 16) == 0 ? 8u : 0u);
-        };
-
-        // pass A: the tile's peak count
-        uint32_t count = 0;
-        for (uint32_t q = t; q < nquad; q += nt) count += __popc(quad_bits(q));
-        for (uint32_t off = 32; off > 0; off >>= 1) count += __shfl_down(count, off, 64);
-        if (lane == 0) wave_cnt[wave] = count;
-        __syncthreads();
-        // look-back by wave 0: 64 predecessors per step, lane l reading
-        // status[j0 - l]; the nearest inclusive prefix ends the walk (a tile
-        // before tile 0 counts as an inclusive prefix of 0)
-        if (wave == 0) {
-            uint64_t agg = 0;
-            for (uint32_t w = 0; w < nwaves; ++w) agg += wave_cnt[w];
-            uint64_t excl = 0;
-            if (item == 0) {
-                if (lane == 0)
-                    __hip_atomic_store(status, (uint64_t(2) << 62) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                if (lane == 0)
-                    __hip_atomic_store(status + item, (uint64_t(1) << 62) | agg, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                int64_t j0 = int64_t(item) - 1;
-                for (;;) {
-                    const int64_t j = j0 - int64_t(lane);
-                    auto load = [&]() {
-                        return j >= 0 ? __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                      : (uint64_t(2) << 62);
-                    };
-                    uint64_t v = load();
-                    uint32_t first = 64;
-                    for (uint32_t spin = 0;; ++spin) {
-                        const uint64_t inc = __ballot((v >> 62) == 2);
-                        const uint64_t zero = __ballot((v >> 62) == 0);
-                        first = inc ? uint32_t(__builtin_ctzll(inc)) : 64u;
-                        const uint64_t need = first >= 63 ? ~uint64_t(0) : ((uint64_t(2) << first) - 1);
-                        if (!(zero & need)) break;
-                        if (spin >= kLookbackSpins) {
-                            if (lane == 0) atomicAdd(err, 1u);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                        if ((v >> 62) == 0) v = load();
-                    }
-                    uint64_t part = lane <= first ? (v & kVal) : 0;
-                    if ((v >> 62) == 0) part = 0;
-                    for (uint32_t off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-                    excl += part;
-                    if (first < 64) break;
-                    j0 -= 64;
-                }
-                if (lane == 0)
-                    __hip_atomic_store(status + item, (uint64_t(2) << 62) | (excl + agg), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (lane == 0) {
-                if (item % per_event == 0) event_off[e] = excl;
-                if (item == n_items - 1) event_off[n_items / per_event] = excl + agg;
-                s_base = excl;
-            }
-        }
-        __syncthreads();
-
-        // pass B: ordered compaction from the tile's offset
-        uint64_t running = s_base;
-        for (uint32_t base = 0; base < nquad; base += nt) {
-            const uint32_t q = base + t;
-            const uint32_t bits = q < nquad ? quad_bits(q) : 0u;
-            const uint32_t c = __popc(bits);
-            const uint64_t b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
-            const uint64_t lt = (1ull << lane) - 1ull;
-            const uint32_t before = __popcll(b0 & lt) + 2 * __popcll(b1 & lt) + 4 * __popcll(b2 & lt);
-            if (lane == 0) wave_cnt[wave] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
-            __syncthreads();
-            uint32_t woff = 0, total = 0;
-            for (uint32_t w = 0; w < nwaves; ++w) {
-                const uint32_t x = wave_cnt[w];
-                woff += w < wave ? x : 0;
-                total += x;
-            }
-            if (bits) {
-                const uint32_t rr = (q << 2) >> log2phi;
-                const uint32_t p0 = (q << 2) & (nphi - 1);
-                const uint32_t cell0 = uint32_t((uint64_t(d) * n_qpt + k0 + rr) * nphi + p0);
-                uint32_t o = woff + before;
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) {
-                    if ((bits >> j) & 1u) {
-                        const uint32_t mk = raw[rr * nphi + p0 + j];
-                        rec[o++] = make_uint2(cell0 + j, mk | (uint32_t(__popc(mk)) << 16));
-                    }
-                }
-            }
-            __syncthreads();
-            uint2 *out = reinterpret_cast<uint2 *>(peaks);
-            for (uint32_t i = t; i < total; i += nt) {
-                const uint64_t pos = running + i;
-                if (pos < capacity) out[pos] = rec[i];
-            }
-            running += total;
-            __syncthreads();
-        }
-    }
-}
-
 // Local maxima of the counting accumulator (the paper's A[B[i]] += 1 form):
 // the rule of k_peaks with the uint32 vote count of a cell in place of its
 // popcount.  Same tiles, halo and ordered compaction; the staged values are
@@ -639,21 +441,6 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
     }
     const size_t lds = peaks_lds_bytes(c, rp, vec);
     KernelTimer t;
-    if (vec && c->tun.peak_one_pass && n_items < (uint64_t(1) << 32)) {
-        // single pass: look-back status words and the ticket start at 0
-        if ((err = launch_fill_u32(c, reinterpret_cast<uint32_t *>(c->d_tile_off), 0u, size_t(n_items) * 2, s)) !=
-                hipSuccess ||
-            (err = launch_fill_u32(c, c->d_counters + 2, 0u, 1, s)) != hipSuccess)
-            return err;
-        const uint32_t per_cu = uint32_t(std::max<size_t>(1, std::min<size_t>(8, (160u << 10) / std::max<size_t>(lds, 1))));
-        const uint32_t grid = uint32_t(std::min<uint64_t>(n_items, uint64_t(c->n_cu) * per_cu));
-        prof_begin(c, "peaks_one", s, &t);
-        hipLaunchKernelGGL(k_peaks_one, dim3(grid), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0, c->spec.n_qpt,
-                           c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold, uint32_t(n_items),
-                           c->d_counters + 2, c->d_tile_off, c->d_counters + 3, event_peak_offsets, peaks, capacity);
-        prof_end(c, s, &t);
-        return hipGetLastError();
-    }
     prof_begin(c, "peaks_count", s, &t);
     if (vec)
         hipLaunchKernelGGL(k_peaks_vec<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads),

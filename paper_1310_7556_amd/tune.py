@@ -1,9 +1,9 @@
 """Autotuner for the library's launch parameters on a given workload.
 
 Swept: the vote's algorithm, tile rows, threads per workgroup and
-workgroups per compute unit; the peak search's tile rows and single- or
-two-pass form; the rz stage's waves per compute unit and LDS counter width
-(the fields of `hough_tuning`).
+workgroups per compute unit; the peak search's tile rows; the rz stage's
+waves per compute unit and LDS counter width (the fields of
+`hough_tuning`).
 
 Stages are tuned one after another (vote, then peaks, then rz), each with
 the earlier stages' winners in place.  A candidate is run `reps` times and
@@ -36,7 +36,7 @@ def vote_space():
 
 
 def peak_space():
-    return [dict(peak_rows=r, peak_one_pass=op) for r in (2, 4, 8, 16, 32, 64) for op in (0, 1)]
+    return [dict(peak_rows=r) for r in (2, 4, 8, 16, 32, 64)]
 
 
 def rz_space():

@@ -157,7 +157,6 @@ def ragged_batch():
                                     dict(vote_algo=3, vote_rows=64, vote_threads=1024), dict(vote_algo=3),
                                     dict(vote_algo=4, vote_rows=64), dict(vote_algo=4, vote_rows=1, vote_threads=64),
                                     dict(vote_algo=2), dict(peak_rows=1), dict(peak_rows=7),
-                                    dict(peak_one_pass=1), dict(peak_one_pass=1, peak_rows=3),
                                     dict(rz_slow_path=1), dict(vote_threads=1024, vote_wgs_per_cu=1)])
 def test_ragged_batch_with_empty_events(H, tuning):
     spec = small_spec()
