@@ -23,13 +23,15 @@
 //      every u >= span past the last bin into a trash counter, and an LDS
 //      atomic add on a lane-private packed counter (8- or 16-bit) whose
 //      return value gives the running count without a read-modify-write
-//      chain; members are padded to a multiple of 8 with ones that never
+//      chain; members are padded to a multiple of 4 with ones that never
 //      vote;
 //   3. the counters are cleared wholesale with 16-byte stores.
 // A candidate with more members than the LDS list or the counter width
 // holds takes the slow path: a uint32 histogram in global scratch, one cot
 // bin at a time.  k_rz_vote is the general kernel (64-bit arithmetic) for
 // specs outside the fast path's range conditions.
+#include <type_traits>
+
 #include "fastdiv.h"
 #include "hough_internal.h"
 
@@ -432,12 +434,12 @@ k_rz_vote_fast(RzParams P)
             }
             nm += __popcll(bal);
         }
-        // pad the member list to a multiple of 8 with members that never
+        // pad the member list to a multiple of 4 with members that never
         // vote: layer 15 is unused (n_layers < 16 on this path), so its
         // (Z + z0_lo) register is 0, and z = 0xFFFFFFFF is then out of range
         // for every cot bin
-        const uint32_t np8 = (nm + 7u) & ~7u;
-        if (nm <= lim && lane < np8 - nm) {
+        const uint32_t np4 = (nm + 3u) & ~3u;
+        if (nm <= lim && lane < np4 - nm) {
             mz[nm + lane] = -1;
             ml[nm + lane] = uint8_t(kMaxLayers - 1);
         }
@@ -457,9 +459,9 @@ k_rz_vote_fast(RzParams P)
 #pragma unroll
                 for (uint32_t l = 0; l + 1 < kMaxLayers; ++l) zn[l] = uint32_t(zln[size_t(min(l, nl - 1)) * P.n_cot]);
                 zn[kMaxLayers - 1] = 0u;
-                // all members in one flat loop, eight per step: two 16-byte
-                // LDS reads give eight z, two 4-byte reads their layers (so
-                // (Z + z0_lo) is a register-indexed move).  Per member: the
+                // all members in one flat loop, eight per step (a last step of
+                // four): 16-byte LDS reads give four z each, 4-byte reads
+                // their layers (so (Z + z0_lo) is a register-indexed move).  Per member: the
                 // bin b = min(mulhi(u, m), n_z0) of u = z - (Z + z0_lo) --
                 // the multiply-high maps every u >= span (out of range, a
                 // padding member, or a lane past the last cot bin whose
@@ -473,14 +475,23 @@ k_rz_vote_fast(RzParams P)
                 // this lane's counter column (row stride 64 dwords)
                 uint32_t *col = hist + lane;
                 int32_t run = INT32_MIN;
-                for (uint32_t m = 0; m < np8; m += 8) {
-                    const uint4 za = mz4[m >> 2], zb = mz4[(m >> 2) + 1];
-                    const uint32_t la = uni(ml4[m >> 2]), lb = uni(ml4[(m >> 2) + 1]);
-                    const uint32_t zm[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
-                    uint32_t b[8], sh[8], old[8];
+                // Q members per step (8, then one step of 4 for the rest)
+                auto step = [&](auto qc, uint32_t m) {
+                    constexpr int Q = decltype(qc)::value;
+                    uint32_t zm[Q], lw[Q / 4];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const uint32_t lq = ((q < 4 ? la : lb) >> (8 * (q & 3))) & 0xFFu;
+                    for (int g = 0; g < Q / 4; ++g) {
+                        const uint4 z4 = mz4[(m >> 2) + g];
+                        zm[4 * g] = z4.x;
+                        zm[4 * g + 1] = z4.y;
+                        zm[4 * g + 2] = z4.z;
+                        zm[4 * g + 3] = z4.w;
+                        lw[g] = uni(ml4[(m >> 2) + g]);
+                    }
+                    uint32_t b[Q], sh[Q], old[Q];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const uint32_t lq = (lw[q >> 2] >> (8 * (q & 3))) & 0xFFu;
                         const uint32_t u = zm[q] - zr[lq];
                         uint32_t t = __umulhi(u, P.bm);
                         if (SHIFT) t >>= P.bs;
@@ -488,17 +499,20 @@ k_rz_vote_fast(RzParams P)
                         sh[q] = b[q] << BSH;   // field offset, taken mod 32
                     }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
+                    for (int q = 0; q < Q; ++q) {
                         // counter dword (b >> PSH) of this lane's column
                         old[q] = atomicAdd(col + ((b[q] >> PSH) << 6), 1u << (sh[q] & 31u));
                     }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
+                    for (int q = 0; q < Q; ++q) {
                         const uint32_t field = __builtin_amdgcn_ubfe(old[q], sh[q], BITS);
                         const int32_t key = int32_t(field << 16) - int32_t(b[q]);
                         run = b[q] < P.n_z0 ? max(run, key) : run;
                     }
-                }
+                };
+                uint32_t m = 0;
+                for (; m + 8 <= np4; m += 8) step(std::integral_constant<int, 8>{}, m);
+                if (m < np4) step(std::integral_constant<int, 4>{}, m);
                 const int32_t fld = (run + 0xFFFF) >> 16;
                 const uint32_t bc = run == INT32_MIN ? 0u : uint32_t(fld) + 1u;
                 const uint32_t bb = uint32_t((fld << 16) - run);
