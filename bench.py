@@ -9,11 +9,19 @@ over the measured step time.  Per-kernel durations come from HIP events
 recorded on the kernels' own stream inside the timed region.
 
 Also reported, in the same line:
+  single_events -- the 100-track event (256 x 256) and the displaced
+              10,000-track event (512 x 512 x 64 d0): time per event, votes/s,
+              peak volume, dominant kernel's HBM roofline, oracle beside it;
   batched  -- 4096 events (lognormal sizes) as one captured HIP graph vs a
               loop of per-event launches on the same GPU, with the vote
               kernel's HBM roofline;
-  serving  -- the continuous-batching request loop (when --serving is on).
-  cpu_baseline -- the CPU oracle timed on this host on one full event.
+  serving  -- the continuous-batching request loop against the plain
+              one-event-per-launch path, with the event pool resident on the
+              device and with async host-to-device copies, each labelled;
+  cpu_baseline -- the CPU oracle timed on this host (bounded sample, median
+              of several passes, CPU model recorded).
+GPU step times are means over the timed steps, with per-step HIP-event
+p10/p50/p90 beside them.
 """
 import argparse
 import json
@@ -62,7 +70,7 @@ def apply_cached_tuning(ctx, torch, spec, n_events, n_hits):
     """The autotuner's cached launch parameters for this workload, applied
     to ctx; returns them, or "default" when the cache has no entry."""
     from paper_1310_7556_amd import tune
-    t = tune.lookup(tune.workload_key(spec, n_events, n_hits, tune.device_name(torch)))
+    t = tune.cached(spec, n_events, n_hits)
     if not t:
         return "default"
     ctx.set_tuning(**t)
@@ -93,14 +101,18 @@ def bench_single(H, torch, steps, warmup):
     torch.cuda.synchronize()
     ctx.kernel_times_reset()
     ctx.set_profiling(True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    marks[0].record(stream)
+    for i in range(steps):
         step()
+        marks[i + 1].record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_profiling(False)
     times = ctx.kernel_times()
+    per_step = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(steps)])
     n_peaks = int(H.offsets_numpy(poff)[-1])
     rzrec = H.rz_numpy(rz, roff)
     members = int(rzrec["n_members"].astype(np.int64).sum())
@@ -110,7 +122,8 @@ def bench_single(H, torch, steps, warmup):
     stage = {k: round(v[1] / v[0], 5) for k, v in times.items() if v[0]}
     dom = max(times, key=lambda k: times[k][1])
     out = dict(ms_per_step=ms, rphi_votes=rphi_votes, rz_votes=rz_votes, n_peaks=n_peaks,
-               n_hits=ev.n_hits, stage_ms=stage, dominant=dom, stream=int(stream.cuda_stream), tuning=tuning)
+               n_hits=ev.n_hits, stage_ms=stage, dominant=dom, stream=int(stream.cuda_stream), tuning=tuning,
+               step_ms_percentiles=percentiles(per_step))
     # roofline of the dominant kernel
     if dom == "rz_vote":
         t = kernel_avg_ms(times, "rz_vote") * 1e-3
@@ -131,6 +144,101 @@ def bench_single(H, torch, steps, warmup):
     out["atomics"] = dict(kernel="rz_vote", space="lds", per_launch=rz_votes, per_s=rz_votes / t_rz,
                           peak_estimate=LDS_ATOMIC_PEAK, frac=round(rz_votes / t_rz / LDS_ATOMIC_PEAK, 5))
     return out, (spec, ev)
+
+
+def percentiles(ms):
+    """p10 / p50 / p90 of per-step HIP-event durations (ms)."""
+    ms = np.asarray(ms, np.float64)
+    return dict(p10=round(float(np.percentile(ms, 10)), 5), p50=round(float(np.percentile(ms, 50)), 5),
+                p90=round(float(np.percentile(ms, 90)), 5), n=int(ms.size))
+
+
+# Algorithmic HBM bytes of the peak kernels: the count pass reads every
+# cell once; the write pass reads every cell again and writes each 8-byte
+# peak record.
+PEAK_KERNEL_BYTES = {
+    "peaks_count": lambda cells, peaks: 2 * cells,
+    "peaks_write": lambda cells, peaks: 2 * cells + 8 * peaks,
+}
+
+
+def bench_event(H, torch, name, steps=20, warmup=3):
+    """One single-event workload without an rz stage (vote + peaks per
+    step): time per event with percentiles, votes/s, the peak volume and the
+    dominant kernel's HBM roofline."""
+    import synth
+    spec = synth.grid_spec(name)
+    ev = synth.gen_config(name)
+    ctx = H.HoughContext(spec, max_events=1, max_hits=ev.n_hits)
+    tuning = apply_cached_tuning(ctx, torch, spec, 1, ev.n_hits)
+    hits = H.DeviceHits.from_batch(ev)
+    acc = ctx.new_acc(1)
+    cap = ctx.cells
+    pk, poff = ctx.new_peaks(cap), ctx.new_offsets(1)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.vote(hits, acc)
+        ctx.peaks(acc, 1, capacity=cap, peaks=pk, offsets=poff)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.kernel_times_reset()
+    ctx.set_profiling(True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    marks[0].record(stream)
+    for i in range(steps):
+        step()
+        marks[i + 1].record(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ctx.set_profiling(False)
+    times = ctx.kernel_times()
+    per_step = [marks[i].elapsed_time(marks[i + 1]) for i in range(steps)]
+    n_peaks = int(H.offsets_numpy(poff)[-1])
+    votes = ev.n_hits * spec["n_qpt"] * spec["n_d0"]
+    dom = max(times, key=lambda k: times[k][1])
+    t = kernel_avg_ms(times, dom) * 1e-3
+    if dom in VOTE_KERNEL_BYTES:
+        byts = VOTE_KERNEL_BYTES[dom](ev.n_hits, ctx.cells)
+    else:
+        byts = PEAK_KERNEL_BYTES.get(dom, lambda cells, peaks: 2 * cells)(ctx.cells, n_peaks)
+    return dict(workload=name, n_hits=ev.n_hits, cells=ctx.cells, votes=votes, peaks=n_peaks,
+                ms_per_event=round(dt * 1e3, 5), step_ms_percentiles=percentiles(per_step),
+                events_per_s=1.0 / dt, votes_per_s=votes / dt,
+                stage_ms={k: round(v[1] / v[0], 5) for k, v in times.items() if v[0]}, tuning=tuning,
+                roofline=dict(kernel=dom, bound="hbm", achieved=round(byts / t / 1e9, 2), peak=HBM_PEAK_GBS,
+                              unit="GB/s", frac=round(byts / t / 1e9 / HBM_PEAK_GBS, 5), bytes_per_launch=byts))
+
+
+def cpu_baseline_event(name, runs=3):
+    """The oracle on a single-event workload without an rz stage, one
+    thread: vote and peaks on the full event, or for the displaced 3D event
+    (6.5e9 votes, over a minute of oracle time) the vote over every 32nd hit
+    scaled to all hits plus the peak search; median of `runs` passes."""
+    import oracle
+    import synth
+    spec = synth.grid_spec(name)
+    ev = synth.gen_config(name)
+    tab = oracle.Tables(spec)
+    sub = 32 if spec["n_d0"] > 1 else 1
+    est = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        A = oracle.vote_mask(tab, ev.layer[::sub], ev.phi[::sub])
+        t1 = time.perf_counter()
+        oracle.peaks(tab, A)
+        t2 = time.perf_counter()
+        est.append((t1 - t0) * ev.n_hits / max(len(ev.layer[::sub]), 1) + (t2 - t1))
+    dt = float(np.median(est))
+    votes = ev.n_hits * spec["n_qpt"] * spec["n_d0"]
+    return dict(value=votes / dt, unit="votes/s", cores=1, cpu_model=cpu_model(), kind="oracle",
+                seconds=round(dt, 4), runs=runs,
+                sample=("the full event: vote and peaks, single thread" if sub == 1 else
+                        f"vote over every {sub}th hit scaled to all {ev.n_hits} hits, plus the peak search, "
+                        "single thread") + f"; median of {runs} passes")
 
 
 def bench_batched(H, torch, reps=5):
@@ -461,6 +569,19 @@ def bench_confirmation(H, torch, reps=5, c4_events=512):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), for the baseline records."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def _oracle_event(args):
     spec, layer, phi = args
     import oracle
@@ -470,9 +591,10 @@ def _oracle_event(args):
     return len(layer)
 
 
-def cpu_baseline_batched(n_events=64):
+def cpu_baseline_batched(n_events=128, runs=5):
     """The oracle on a sample of the 4096-event batch, one event per worker
-    process across the host cores (vote and peaks, as in the batched path)."""
+    process across the host cores (vote and peaks, as in the batched path);
+    the median of `runs` passes over the same sample, pool start-up excluded."""
     import multiprocessing as mp
     import synth
     name = "c4_batch_4096"
@@ -480,26 +602,52 @@ def cpu_baseline_batched(n_events=64):
     batch = synth.gen_batch(name, n_events)
     work = [(spec, batch.event(e).layer, batch.event(e).phi) for e in range(n_events)]
     cores = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
+    secs = []
     with mp.get_context("spawn").Pool(cores) as pool:
-        hits = sum(pool.map(_oracle_event, work, chunksize=1))
-    dt = time.perf_counter() - t0
+        pool.map(_oracle_event, work[:cores], chunksize=1)          # workers started and warm
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            hits = sum(pool.map(_oracle_event, work, chunksize=1))
+            secs.append(time.perf_counter() - t0)
+    dt = float(np.median(secs))
     return dict(value=hits * spec["n_qpt"] / dt, unit="votes/s", events_per_s=n_events / dt, cores=cores,
-                kind="oracle", seconds=round(dt, 2),
+                cpu_model=cpu_model(), kind="oracle", seconds=round(dt, 3),
+                seconds_min_max=[round(min(secs), 3), round(max(secs), 3)], runs=runs,
                 sample=f"the first {n_events} events of the 4096-event batch ({hits} hits): vote and peaks, "
-                       f"one event per process on {cores} host cores (pool start-up included)")
+                       f"one event per process on {cores} host cores; median of {runs} passes")
 
 
-def cpu_baseline(spec, ev):
+def cpu_baseline(spec, ev, runs=5):
+    """The oracle on the headline event, one thread: each of `runs` passes
+    does the whole vote and peak search and the rz stage on one fifth of the
+    candidates (every runs-th peak, a different fifth each pass), and its
+    step time is the vote and peak time plus the rz time scaled to all
+    candidates; the value is the median of the passes' rates."""
     import oracle
     tab = oracle.Tables(spec)
-    t0 = time.perf_counter()
-    A, pk, r = oracle.run_event(tab, ev.layer, ev.phi, ev.z)
-    dt = time.perf_counter() - t0
+    est, parts = [], []
+    for r in range(runs):
+        t0 = time.perf_counter()
+        A = oracle.vote_mask(tab, ev.layer, ev.phi)
+        t1 = time.perf_counter()
+        pk = oracle.peaks(tab, A)
+        t2 = time.perf_counter()
+        sub = pk[r::runs]
+        oracle.rz(tab, ev.layer, ev.phi, ev.z, sub)
+        t3 = time.perf_counter()
+        step = (t1 - t0) + (t2 - t1) + (t3 - t2) * len(pk) / max(len(sub), 1)
+        est.append(step)
+        parts.append((t1 - t0, t2 - t1, t3 - t2))
     votes = ev.n_hits * spec["n_qpt"] * spec["n_d0"]
-    return dict(value=votes / dt, unit="votes/s", cores=1, kind="oracle", seconds=round(dt, 2),
-                sample=f"one full 1000-track event ({ev.n_hits} hits): vote, peaks and rz over all "
-                       f"{len(pk)} peaks, single thread")
+    dt = float(np.median(est))
+    med = np.median(np.array(parts), axis=0)
+    return dict(value=votes / dt, unit="votes/s", cores=1, cpu_model=cpu_model(), kind="oracle",
+                seconds=round(dt, 3), seconds_min_max=[round(min(est), 3), round(max(est), 3)], runs=runs,
+                stage_seconds=dict(vote=round(med[0], 4), peaks=round(med[1], 4),
+                                   rz_fifth=round(med[2], 4)),
+                sample=f"the 1000-track event ({ev.n_hits} hits, {len(pk)} peaks), single thread: per pass "
+                       f"the full vote and peak search plus rz on every {runs}th candidate (a different "
+                       f"{runs}th each pass) scaled to all candidates; median of {runs} passes")
 
 
 def main():
@@ -546,11 +694,19 @@ def main():
         paper_context=("the paper prints no absolute timings; its Figure 2 (2048x2048 grid, toy Monte "
                        "Carlo) has a Tesla K20c about as fast as 2x Xeon E5-2697v2, Xeon Phi 7120P 3x and "
                        "i7-3770 5x slower at 5000 tracks"),
+        step_ms_percentiles=single["step_ms_percentiles"],
         peaks_per_event=single["n_peaks"],
         stage_ms=single["stage_ms"],
         tuning=single["tuning"],
         roofline=single["roofline"],
     )
+    res["single_events"] = {}
+    for name in ("c1_single_100trk", "c3_pileup_displaced_3d"):
+        log(f"{name} ...")
+        r = bench_event(H, torch, name)
+        res["single_events"][name] = r
+        log(f"{name}: {r['ms_per_event']} ms/event, dominant {r['roofline']['kernel']} "
+            f"{r['roofline']['frac']:.3f} of HBM")
     if not args.no_batched:
         log("c4 batched vs plain ...")
         res["batched"] = bench_batched(H, torch)
@@ -573,6 +729,9 @@ def main():
     if not args.no_cpu:
         log("cpu oracle baseline ...")
         res["cpu_baseline"] = cpu_baseline(spec, ev)
+        for name, r in res["single_events"].items():
+            log(f"cpu oracle baseline, {name} ...")
+            r["cpu_baseline"] = cpu_baseline_event(name)
         if not args.no_batched:
             log("cpu oracle baseline, batched sample ...")
             res["batched"]["cpu_baseline"] = cpu_baseline_batched()

@@ -1,7 +1,7 @@
 /*
  * hough.h -- C ABI of the MI355X (gfx950) Hough-transform track finder.
  *
- * The paper's method (Section 3, "Hough Transform Algorithm") has two steps:
+ * The paper's method (Section 4, "Hough Transform Algorithm") has two steps:
  * every hit adds votes to the cells of a discretised (curvature, azimuth)
  * parameter space that are consistent with it, and cells with many votes are
  * then found as local maxima of that space.  This library computes:
@@ -14,7 +14,7 @@
  *                    a d0 axis; phi0 wraps, q/pT and d0 do not
  *   hough_rz_refine  the confirmation step the paper leaves to "more
  *                    expensive computations" (end of the first paragraph of
- *                    Section 3): per candidate cell, its member hits vote in
+ *                    Section 4): per candidate cell, its member hits vote in
  *                    a (cot theta, z0) grid and the argmax is reported
  *
  * Geometry.  Curvature rho = 0.299792458e-3 * b_tesla * q/pT [1/mm]; B along
@@ -180,17 +180,23 @@ typedef struct {
  * n_d0 == 1), builds the FP64 tables on the host, allocates tables and
  * scratch on `device` and uploads the tables (a blocking host-to-device
  * copy, done once).  *out receives the context; nothing is allocated on
- * failure.  Returns HOUGH_EINVAL, HOUGH_ENOMEM or HOUGH_EDEVICE on error. */
+ * failure.  Returns HOUGH_EINVAL, HOUGH_ENOMEM or HOUGH_EDEVICE on error.
+ * The tables carry what Section 6.1 lists among the GPU optimisations,
+ * keeping expensive trigonometric functions out of the kernels: every asin
+ * of the vote and of the rz stage is evaluated here, once.  The context then
+ * stays resident on the device across calls, the data persistence that
+ * Section 6.2 uses to avoid re-allocating for every frame offloaded. */
 int hough_create(const hough_grid_spec *spec, const hough_limits *limits,
                  int device, hough_ctx **out);
 
-/* Frees the context's device memory.  NULL is accepted.  Work still
- * enqueued with this context must have completed. */
+/* Frees the context's device memory (the resident tables and scratch of
+ * hough_create, Section 6.2).  NULL is accepted.  Work still enqueued with
+ * this context must have completed. */
 void hough_destroy(hough_ctx *ctx);
 
 /* ---- hot path ---------------------------------------------------------- */
 
-/* Step 1, voting (Section 3: increment the voxels each hit maps to; the
+/* Step 1, voting (Section 4: increment the voxels each hit maps to; the
  * Discussion's A[B[i]] += 1 in its layer-mask form).  For every event e,
  * every hit h of e with layer l < n_layers and every reachable row (d, k):
  *     acc[e][d][k][(phi_h - O[l][d][k]) >> (32 - log2 n_phi)] |= 1 << l.
@@ -199,7 +205,7 @@ void hough_destroy(hough_ctx *ctx);
  * n_hits <= max_hits (HOUGH_ELIMIT).  hits->z_um is not read. */
 int hough_vote(hough_ctx *ctx, const hough_hits *hits, uint16_t *acc, void *stream);
 
-/* Step 2, local maxima (Section 3: finding cells with many votes amounts to
+/* Step 2, local maxima (Section 4: finding cells with many votes amounts to
  * looking for local maxima).  A cell c of event e is a peak iff
  * popcount(acc[c]) >= threshold and popcount(acc[c]) >= popcount of each
  * neighbour (3x3 in (q/pT, phi0), 3x3x3 when n_d0 > 1; phi0 periodic,
@@ -237,7 +243,7 @@ int hough_peaks_count(hough_ctx *ctx, const uint32_t *counts, uint32_t n_events,
 
 /* Candidate confirmation, plateau de-duplication.  The local-maximum rule
  * is non-strict, so a flat-topped ridge of votes gives several adjacent
- * peaks (Section 3 leaves the confirmation of candidates to later, more
+ * peaks (Section 4 leaves the confirmation of candidates to later, more
  * expensive steps).  Two peaks of one event are adjacent when their cells
  * are neighbours in the local-maximum neighbourhood (3x3, 3x3x3 with a d0
  * axis; phi0 periodic, q/pT and d0 not); a cluster is a connected component
@@ -277,7 +283,10 @@ int hough_peak_clusters(hough_ctx *ctx, const hough_peak *peaks, uint64_t peak_c
  * the peaks were found from (same n_events); peaks/event_peak_offsets are
  * hough_peaks' outputs, clusters/event_cluster_offsets hough_peak_clusters'.
  * fp64 arithmetic; members are summed in a fixed order on the device, so
- * results agree with a serial evaluation to rounding. */
+ * results agree with a serial evaluation to rounding.  The member search
+ * uses the context's (layer, azimuth bucket) index of the hits, which exists
+ * only on a grid with an rz stage or when limits.max_peaks > 0 was given at
+ * hough_create: otherwise HOUGH_EINVAL, before anything is enqueued. */
 int hough_cluster_fit(hough_ctx *ctx, const hough_hits *hits, const hough_peak *peaks, uint64_t peak_capacity,
                       const uint64_t *event_peak_offsets, const hough_cluster *clusters, uint64_t capacity,
                       const uint64_t *event_cluster_offsets, hough_fit *out, void *stream);
@@ -318,30 +327,48 @@ void hough_graph_destroy(hough_graph *graph);
 
 /* ---- serving support ---------------------------------------------------- */
 
-/* Micro-batch assembly for the serving loop: copies n events out of a
+/* Micro-batch assembly for the serving loop (keeping events resident on the
+ * device across frames, Section 6.2): copies n events out of a
  * device-resident source SoA into one contiguous destination SoA.  Event i
  * occupies source hits [src_off[i], src_off[i] + len[i]) and lands at
  * destination hits [dst_off[i], dst_off[i] + len[i]); dst_off has n + 1
  * entries and dst_off[n] is the destination's hit count, so dst_off is
  * directly usable as the destination's event_offsets.  src_off, len and
- * dst_off are device arrays; the caller guarantees every range lies inside
- * its buffer.  z pointers may both be NULL.  Asynchronous on `stream`. */
+ * dst_off are device arrays; the caller guarantees every source range lies
+ * inside its buffer.  The destination arrays hold dst_capacity hits: no hit
+ * is written at or past dst_capacity (such hits are dropped, so the caller
+ * checks dst_off[n] <= dst_capacity before relying on the result).  z
+ * pointers may both be NULL.  Asynchronous on `stream`. */
 int hough_gather_events(const uint8_t *src_layer, const uint32_t *src_phi, const int32_t *src_z,
                         const uint64_t *src_off, const uint64_t *len, const uint64_t *dst_off,
                         uint32_t n, uint8_t *dst_layer, uint32_t *dst_phi, int32_t *dst_z,
-                        void *stream);
+                        uint64_t dst_capacity, void *stream);
 
 /* ---- helpers (not on the hot path) ------------------------------------ */
 
 /* HOUGH_OK if the spec is valid, else HOUGH_EINVAL.  Host only. */
 int hough_check_spec(const hough_grid_spec *spec);
 
-/* The library's own host tables, for inspection: O and V as [l][d][k]
+/* The library's own host tables, rebuilt from a spec (FP64, the same code
+ * hough_create runs; Section 6.1's trigonometry kept off the device), for
+ * inspection without a device: O and V as [l][d][k]
  * (n_layers * n_d0 * n_qpt entries each, V = 1 if reachable), Z as [k][l][j]
  * (n_qpt * n_layers * n_cot entries; may be NULL when n_z0 == 0).  Host
  * only, needs no device.  Buffer sizes are checked against nOV and nZ. */
 int hough_build_tables(const hough_grid_spec *spec, uint32_t *O, uint8_t *V, size_t nOV,
                        int32_t *Z, size_t nZ);
+
+/* The tables a context uploaded at hough_create, read back from its device
+ * (blocking copies; the stream order of other work is not involved).  O and
+ * V as [l][d][k] (n_layers * n_d0 * n_qpt entries each, V = 1 if the row is
+ * reachable from layer l), Z as [k][l][j] (n_qpt * n_layers * n_cot
+ * entries, grids with an rz stage), and Zl = Z + z0_lo, the copy the rz
+ * kernel reads when every such sum fits int32 arithmetic exactly (same
+ * layout).  Any output pointer may be NULL to skip it; sizes are checked
+ * against nOV, nZ and nZl, and asking for Z without an rz stage or for Zl
+ * when the context keeps none gives HOUGH_EINVAL. */
+int hough_get_tables(const hough_ctx *ctx, uint32_t *O, uint8_t *V, size_t nOV, int32_t *Z, size_t nZ,
+                     int32_t *Zl, size_t nZl);
 
 /* Kernel tuning.  Values outside the supported set give HOUGH_EINVAL and
  * leave the previous tuning in place. */

@@ -4,7 +4,7 @@ A numpy-facing wrapper over oracle.c (plain C, built with gcc -O2).  Only the
 test-suite, the smoke check and the benchmark's CPU-baseline leg may import
 this package; the product library and its Python binding never do.
 
-Functions follow Section 3 of the paper (voting, then local maxima) and the
+Functions follow Section 4 of the paper (voting, then local maxima) and the
 Discussion section's counting form; see oracle.c for the exact definitions
 and the readings of points the paper leaves open.
 """

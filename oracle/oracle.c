@@ -6,7 +6,7 @@
  * path never does.  It shares no code, header, table or helper with the GPU
  * library: it builds its own tables from the definitions below.
  *
- * What is computed (Section 3 of the paper, "Hough Transform Algorithm"):
+ * What is computed (Section 4 of the paper, "Hough Transform Algorithm"):
  *   step 1 -- every hit adds a vote to each parameter-space cell whose track
  *             would contain it (the two-variable curvature/azimuth grid);
  *   step 2 -- cells with many votes are candidates; finding them is a
@@ -222,7 +222,7 @@ uint64_t orc_peaks(const orc_spec *g, const uint16_t *A,
 }
 
 /* Local maxima of the counting accumulator (the paper's A[B[i]] += 1 form,
- * Section 7): the same rule as orc_peaks with the cell's vote count in place
+ * Section 8): the same rule as orc_peaks with the cell's vote count in place
  * of its popcount -- count >= threshold and >= the count of every
  * neighbour (3x3, 3x3x3 with a d0 axis; phi0 periodic).  Ascending cell
  * order; returns the true number of peaks, records past cap dropped. */
@@ -355,7 +355,7 @@ uint64_t orc_rz(const orc_spec *g, const uint32_t *O, const uint8_t *V, const in
 /* ---- candidate confirmation: plateau clusters --------------------------
  *
  * The non-strict local-maximum rule reports every cell of a flat-topped
- * ridge, so one track can give several adjacent peaks (Section 3 leaves the
+ * ridge, so one track can give several adjacent peaks (Section 4 leaves the
  * confirmation of candidates to more expensive later computations).  Two
  * peaks of one event are adjacent when their cells are neighbours in the
  * local-maximum neighbourhood (3x3 in (q/pT, phi0), 3x3x3 with a d0 axis;

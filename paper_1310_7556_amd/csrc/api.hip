@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "fastdiv.h"
 #include "hough_internal.h"
@@ -184,7 +185,7 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = std::min<size_t>(size_t(lds) - 512, 65536);   // headroom for static LDS
-        c->max_lds_direct = c->max_lds;
+    c->max_lds_direct = c->max_lds;
     while ((1u << c->log2_phi) < spec->n_phi) ++c->log2_phi;
     c->shift = 32 - c->log2_phi;
     c->rows = spec->n_d0 * spec->n_qpt;
@@ -346,6 +347,9 @@ int hough_cluster_fit(hough_ctx *ctx, const hough_hits *hits, const hough_peak *
     if ((reinterpret_cast<uintptr_t>(peaks) & 7) || (reinterpret_cast<uintptr_t>(clusters) & 7) ||
         (reinterpret_cast<uintptr_t>(out) & 7))
         return HOUGH_EINVAL;
+    // the member search reads the (layer, azimuth bucket) index, which the
+    // context keeps only with an rz grid or limits.max_peaks > 0
+    if (ctx->bucket_bits == 0 || !ctx->d_phi_b || !ctx->d_bucket_off) return HOUGH_EINVAL;
     if (hits->n_events > ctx->lim.max_events || hits->n_hits > ctx->lim.max_hits) return HOUGH_ELIMIT;
     DeviceGuard guard(ctx->device);
     const hipError_t e = launch_fit(ctx, hits, peaks, peak_capacity, event_peak_offsets, clusters, capacity,
@@ -438,13 +442,33 @@ void hough_graph_destroy(hough_graph *graph)
 int hough_gather_events(const uint8_t *src_layer, const uint32_t *src_phi, const int32_t *src_z,
                         const uint64_t *src_off, const uint64_t *len, const uint64_t *dst_off,
                         uint32_t n, uint8_t *dst_layer, uint32_t *dst_phi, int32_t *dst_z,
-                        void *stream)
+                        uint64_t dst_capacity, void *stream)
 {
     if (n && (!src_layer || !src_phi || !src_off || !len || !dst_off || !dst_layer || !dst_phi))
         return HOUGH_EINVAL;
     if ((src_z == nullptr) != (dst_z == nullptr)) return HOUGH_EINVAL;
     const hipError_t e = launch_gather_events(src_layer, src_phi, src_z, src_off, len, dst_off, n, dst_layer,
-                                              dst_phi, dst_z, static_cast<hipStream_t>(stream));
+                                              dst_phi, dst_z, dst_capacity, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
+}
+
+int hough_get_tables(const hough_ctx *ctx, uint32_t *O, uint8_t *V, size_t nOV, int32_t *Z, size_t nZ,
+                     int32_t *Zl, size_t nZl)
+{
+    if (!ctx) return HOUGH_EINVAL;
+    const hough_grid_spec &g = ctx->spec;
+    const size_t need = size_t(g.n_layers) * ctx->rows;
+    const size_t needz = g.n_z0 ? size_t(g.n_qpt) * g.n_layers * g.n_cot : 0;
+    if ((O && nOV < need) || (V && nOV < need)) return HOUGH_EINVAL;
+    if (Z && (!g.n_z0 || nZ < needz)) return HOUGH_EINVAL;
+    // the (Z + z0_lo) copy exists only when the rz stage takes its 32-bit path
+    if (Zl && (!ctx->rz_fast || !ctx->d_Zl || nZl < needz)) return HOUGH_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipSuccess;
+    if (O) e = hipMemcpy(O, ctx->d_O, need * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && V) e = hipMemcpy(V, ctx->d_V, need, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && Z) e = hipMemcpy(Z, ctx->d_Z, needz * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && Zl) e = hipMemcpy(Zl, ctx->d_Zl, needz * 4, hipMemcpyDeviceToHost);
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 

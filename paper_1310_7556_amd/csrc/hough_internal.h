@@ -116,6 +116,22 @@ hipError_t launch_vote(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStre
 hipError_t launch_vote_count(hough_ctx *c, const hough_hits *h, uint32_t *counts, hipStream_t s);
 hipError_t launch_peaks_count(hough_ctx *c, const uint32_t *counts, uint32_t n_events, uint2 *peaks,
                               uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s);
+// Scratch of the peak search: per-tile peak counts, their exclusive prefix
+// and the block sums of a multi-block scan over them.
+struct PeakScratch {
+    uint32_t *tile_counts;        // [tiles]
+    uint64_t *tile_off;           // [tiles + 1]
+    uint64_t *scan_part;          // [scan_blocks_max]
+    uint64_t *scan_off;           // [scan_blocks_max + 1]
+    uint64_t scan_blocks_max;
+};
+PeakScratch ctx_peak_scratch(hough_ctx *c);
+// Number of tiles the peak search of n_events accumulators at `acc` uses.
+uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc);
+// timed = false: no per-kernel timing (no HIP events are created)
+hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
+                        uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s,
+                        const PeakScratch &ps, bool timed = true);
 hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
                         uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s);
 hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
@@ -123,7 +139,7 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
                      uint64_t capacity, uint64_t *event_rz_offsets, hipStream_t s);
 hipError_t launch_gather_events(const uint8_t *sl, const uint32_t *sp, const int32_t *sz, const uint64_t *src_off,
                                 const uint64_t *len, const uint64_t *dst_off, uint32_t n, uint8_t *dl,
-                                uint32_t *dp, int32_t *dz, hipStream_t s);
+                                uint32_t *dp, int32_t *dz, uint64_t cap, hipStream_t s);
 uint32_t vote_rows(const hough_ctx *c);
 hipError_t launch_vote_gaps(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
 hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
@@ -138,6 +154,11 @@ uint64_t max_peak_tiles(const hough_ctx *c);
 uint64_t scan_blocks(uint64_t n);
 hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
                               uint64_t stride_out, uint64_t *out_strided, hipStream_t s);
+// The same with explicit block-sum scratch (scan_part[blocks_max],
+// scan_off[blocks_max + 1]); timed = false skips per-kernel timing.
+hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
+                              uint64_t stride_out, uint64_t *out_strided, hipStream_t s, uint64_t *scan_part,
+                              uint64_t *scan_off, uint64_t blocks_max, bool timed);
 
 // Plateau clusters of a peak list (lock-free union-find, see k_cluster.hip).
 uint64_t cluster_blocks(uint64_t n);

@@ -1,7 +1,7 @@
 // Candidate confirmation, first part: plateau clusters of the peak list.
 //
 // The non-strict local-maximum rule keeps every cell of a flat-topped ridge,
-// so one track yields several adjacent peaks (Section 3 leaves the
+// so one track yields several adjacent peaks (Section 4 leaves the
 // confirmation of candidates to later, more expensive computations).  Two
 // peaks of one event are adjacent when their cells are neighbours in the
 // local-maximum neighbourhood (3x3, 3x3x3 with a d0 axis; phi0 periodic);

@@ -1,5 +1,5 @@
-// Step 2 of the transform: local maxima of the accumulator (Section 3, second
-// step; Section 7 notes this search is regular in memory but reduction-heavy).
+// Step 2 of the transform: local maxima of the accumulator (Section 4, second
+// step; Section 8 notes this search is regular in memory but reduction-heavy).
 //
 // A cell is a peak iff popcount >= threshold and >= the popcount of each
 // neighbour in its 3x3 (q/pT, phi0) window, 3x3x3 with a d0 axis; phi0 is
@@ -12,6 +12,7 @@
 #include "hough_internal.h"
 
 namespace hough {
+
 
 template <bool WRITE>
 __global__ void __launch_bounds__(256)
@@ -426,8 +427,24 @@ uint32_t fit_rows(const hough_ctx *c, bool vec)
 
 }  // namespace
 
+uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc)
+{
+    const bool vec = c->spec.n_phi >= 8 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0 &&
+                     fit_rows(c, true) > 0;
+    const uint32_t rp = fit_rows(c, vec);
+    if (rp == 0) return 0;
+    const uint32_t n_kt = (c->spec.n_qpt + rp - 1) / rp;
+    return uint64_t(n_events) * c->spec.n_d0 * n_kt;
+}
+
+PeakScratch ctx_peak_scratch(hough_ctx *c)
+{
+    return PeakScratch{c->d_tile_counts, c->d_tile_off, c->d_scan_part, c->d_scan_off, c->scan_blocks_max};
+}
+
 hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
-                        uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s)
+                        uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s, const PeakScratch &ps,
+                        bool timed)
 {
     hipError_t err;
     const bool vec = c->spec.n_phi >= 8 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0 &&
@@ -437,36 +454,45 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
     const uint32_t n_kt = (c->spec.n_qpt + rp - 1) / rp;
     const uint64_t n_items = uint64_t(n_events) * c->spec.n_d0 * n_kt;
     if (n_events == 0) {
-        return launch_scan_counts(c, c->d_tile_counts, 0, c->d_tile_off, 1, event_peak_offsets, s);
+        return launch_scan_counts(c, ps.tile_counts, 0, ps.tile_off, 1, event_peak_offsets, s, ps.scan_part,
+                                  ps.scan_off, ps.scan_blocks_max, timed);
     }
     const size_t lds = peaks_lds_bytes(c, rp, vec);
     KernelTimer t;
-    prof_begin(c, "peaks_count", s, &t);
+    t.name = nullptr;
+    if (timed) prof_begin(c, "peaks_count", s, &t);
     if (vec)
         hipLaunchKernelGGL(k_peaks_vec<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads),
                            peaks_lds_bytes(c, rp, true, false),
                            s, acc, c->spec.n_d0, c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt,
-                           c->spec.threshold, c->d_tile_counts, c->d_tile_off, peaks, capacity);
+                           c->spec.threshold, ps.tile_counts, ps.tile_off, peaks, capacity);
     else
         hipLaunchKernelGGL(k_peaks<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
                            c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
-                           c->d_tile_counts, c->d_tile_off, peaks, capacity);
-    prof_end(c, s, &t);
+                           ps.tile_counts, ps.tile_off, peaks, capacity);
+    if (timed) prof_end(c, s, &t);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    if ((err = launch_scan_counts(c, c->d_tile_counts, n_items, c->d_tile_off,
-                                  uint64_t(c->spec.n_d0) * n_kt, event_peak_offsets, s)) != hipSuccess)
+    if ((err = launch_scan_counts(c, ps.tile_counts, n_items, ps.tile_off, uint64_t(c->spec.n_d0) * n_kt,
+                                  event_peak_offsets, s, ps.scan_part, ps.scan_off, ps.scan_blocks_max,
+                                  timed)) != hipSuccess)
         return err;
-    prof_begin(c, "peaks_write", s, &t);
+    if (timed) prof_begin(c, "peaks_write", s, &t);
     if (vec)
         hipLaunchKernelGGL(k_peaks_vec<true>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
                            c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
-                           c->d_tile_counts, c->d_tile_off, peaks, capacity);
+                           ps.tile_counts, ps.tile_off, peaks, capacity);
     else
         hipLaunchKernelGGL(k_peaks<true>, dim3(uint32_t(n_items)), dim3(kPeakThreads), lds, s, acc, c->spec.n_d0,
                            c->spec.n_qpt, c->spec.n_phi, c->log2_phi, rp, n_kt, c->spec.threshold,
-                           c->d_tile_counts, c->d_tile_off, peaks, capacity);
-    prof_end(c, s, &t);
+                           ps.tile_counts, ps.tile_off, peaks, capacity);
+    if (timed) prof_end(c, s, &t);
     return hipGetLastError();
+}
+
+hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
+                        uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s)
+{
+    return launch_peaks(c, acc, n_events, peaks, capacity, event_peak_offsets, s, ctx_peak_scratch(c), true);
 }
 
 hipError_t launch_peaks_count(hough_ctx *c, const uint32_t *counts, uint32_t n_events, uint2 *peaks,

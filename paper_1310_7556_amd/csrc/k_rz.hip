@@ -1,5 +1,5 @@
 // rz refinement of candidate cells: the "more expensive computations to
-// confirm" that Section 3 leaves to follow the local-maximum search.
+// confirm" that Section 4 leaves to follow the local-maximum search.
 //
 // Candidates of an event are its peaks (in list order), or the first
 // rz_max_candidates of them by (popcount desc, cell asc).  For a candidate

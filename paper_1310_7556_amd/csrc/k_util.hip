@@ -120,10 +120,11 @@ __global__ void __launch_bounds__(256)
 k_gather_events(const uint8_t *__restrict__ sl, const uint32_t *__restrict__ sp, const int32_t *__restrict__ sz,
                 const uint64_t *__restrict__ src_off, const uint64_t *__restrict__ len,
                 const uint64_t *__restrict__ dst_off, uint32_t n, uint8_t *__restrict__ dl,
-                uint32_t *__restrict__ dp, int32_t *__restrict__ dz)
+                uint32_t *__restrict__ dp, int32_t *__restrict__ dz, uint64_t cap)
 {
     for (uint32_t e = blockIdx.y; e < n; e += gridDim.y) {
-        const uint64_t s0 = src_off[e], d0 = dst_off[e], m = len[e];
+        const uint64_t s0 = src_off[e], d0 = min(dst_off[e], cap);
+        const uint64_t m = min(len[e], cap - d0);   // nothing lands at or past cap
         for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
              i += uint64_t(gridDim.x) * blockDim.x) {
             dl[d0 + i] = sl[s0 + i];
@@ -135,11 +136,11 @@ k_gather_events(const uint8_t *__restrict__ sl, const uint32_t *__restrict__ sp,
 
 hipError_t launch_gather_events(const uint8_t *sl, const uint32_t *sp, const int32_t *sz, const uint64_t *src_off,
                                 const uint64_t *len, const uint64_t *dst_off, uint32_t n, uint8_t *dl,
-                                uint32_t *dp, int32_t *dz, hipStream_t s)
+                                uint32_t *dp, int32_t *dz, uint64_t cap, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
+    if (n == 0 || cap == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_events, dim3(64, std::min(n, 65535u)), dim3(256), 0, s, sl, sp, sz, src_off, len,
-                       dst_off, n, dl, dp, dz);
+                       dst_off, n, dl, dp, dz, cap);
     return hipGetLastError();
 }
 
@@ -160,24 +161,33 @@ uint64_t scan_blocks(uint64_t n)
 }
 
 hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
-                              uint64_t stride_out, uint64_t *out_strided, hipStream_t s)
+                              uint64_t stride_out, uint64_t *out_strided, hipStream_t s, uint64_t *scan_part,
+                              uint64_t *scan_off, uint64_t blocks_max, bool timed)
 {
     KernelTimer t;
+    t.name = nullptr;
     const uint64_t stride = stride_out ? stride_out : 1;
     const uint64_t nb = scan_blocks(n);
-    prof_begin(c, "scan_counts", s, &t);
-    if (nb <= 2 || nb > c->scan_blocks_max) {
+    if (timed) prof_begin(c, "scan_counts", s, &t);
+    if (nb <= 2 || nb > blocks_max) {
         hipLaunchKernelGGL(k_scan_counts<uint32_t>, dim3(1), dim3(1024), 0, s, counts, n, offsets, stride,
                            out_strided);
     } else {
-        hipLaunchKernelGGL(k_scan_partials, dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, counts, n, c->d_scan_part);
-        hipLaunchKernelGGL(k_scan_counts<uint64_t>, dim3(1), dim3(1024), 0, s, c->d_scan_part, nb, c->d_scan_off,
+        hipLaunchKernelGGL(k_scan_partials, dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, counts, n, scan_part);
+        hipLaunchKernelGGL(k_scan_counts<uint64_t>, dim3(1), dim3(1024), 0, s, scan_part, nb, scan_off,
                            uint64_t(1), static_cast<uint64_t *>(nullptr));
-        hipLaunchKernelGGL(k_scan_apply, dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, counts, n, c->d_scan_off,
+        hipLaunchKernelGGL(k_scan_apply, dim3(uint32_t(nb)), dim3(kScanThreads), 0, s, counts, n, scan_off,
                            offsets, stride, out_strided);
     }
-    prof_end(c, s, &t);
+    if (timed) prof_end(c, s, &t);
     return hipGetLastError();
+}
+
+hipError_t launch_scan_counts(hough_ctx *c, const uint32_t *counts, uint64_t n, uint64_t *offsets,
+                              uint64_t stride_out, uint64_t *out_strided, hipStream_t s)
+{
+    return launch_scan_counts(c, counts, n, offsets, stride_out, out_strided, s, c->d_scan_part, c->d_scan_off,
+                              c->scan_blocks_max, true);
 }
 
 }  // namespace hough

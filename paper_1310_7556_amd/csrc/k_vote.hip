@@ -1,5 +1,5 @@
 // Step 1 of the transform: every hit votes into every reachable row of the
-// accumulator (Section 3, first step; the Discussion's indirect update
+// accumulator (Section 4, first step; the Discussion's indirect update
 // A[B[i]] += 1, here in its layer-bitmask OR form).
 //
 // Work item = (event, tile of R consecutive rows).  A persistent grid pulls
@@ -9,12 +9,12 @@
 // scalars, and each vote is: subtract, shift, LDS atomic OR.  The finished
 // tile is packed to uint16 and written to HBM once, with coalesced stores.
 // This is the paper's GPU recipe (global atomics replaced by shared-memory
-// atomics, Section 5.1) re-tiled for 64-wide wavefronts and 160 KB LDS.
+// atomics, Section 6.1) re-tiled for 64-wide wavefronts and 160 KB LDS.
 #include "hough_internal.h"
 
 namespace hough {
 
-// COUNT: the paper's counting form A[B[i]] += 1 (Section 7) -- an atomic
+// COUNT: the paper's counting form A[B[i]] += 1 (Section 8) -- an atomic
 // add of 1 per vote into the uint32 tile, written out as uint32 counts --
 // instead of the OR of the layer bit packed to uint16 masks.
 template <int R, bool COUNT>

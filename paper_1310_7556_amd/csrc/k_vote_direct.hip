@@ -1,4 +1,4 @@
-// Step 1 of the transform in its direct bin-occupancy form (Section 3, first
+// Step 1 of the transform in its direct bin-occupancy form (Section 4, first
 // step; the Discussion's A[B[i]] += 1 in layer-mask form), the default vote
 // algorithm.
 //

@@ -1,4 +1,4 @@
-// Step 1 of the transform in its exact gap form (Section 3, first step; the
+// Step 1 of the transform in its exact gap form (Section 4, first step; the
 // Discussion's A[B[i]] += 1 in layer-mask form), the default vote algorithm.
 //
 // A cell (row r, bin p) gets layer bit l iff some hit of layer l lies in the

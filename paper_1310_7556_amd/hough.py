@@ -23,7 +23,7 @@ EXPORTED = [
     "hough_set_profiling", "hough_kernel_times", "hough_kernel_times_reset",
     "hough_strerror", "hough_last_error", "hough_device_cus", "hough_gather_events",
     "hough_vote_count", "hough_peaks_count", "hough_peak_clusters",
-    "hough_cluster_fit",
+    "hough_cluster_fit", "hough_get_tables",
 ]
 
 PEAK_DTYPE = np.dtype([("cell", np.uint32), ("mask", np.uint16), ("popcount", np.uint16)])
@@ -99,7 +99,8 @@ def load_library():
         "hough_strerror": ([i32], C.c_char_p),
         "hough_last_error": ([P], C.c_char_p),
         "hough_device_cus": ([P], i32),
-        "hough_gather_events": ([P, P, P, P, P, P, u32, P, P, P, P], i32),
+        "hough_gather_events": ([P, P, P, P, P, P, u32, P, P, P, u64, P], i32),
+        "hough_get_tables": ([P, P, P, C.c_size_t, P, C.c_size_t, P, C.c_size_t], i32),
         "hough_vote_count": ([P, P, P, P], i32),
         "hough_peaks_count": ([P, P, u32, P, u64, P, P], i32),
         "hough_peak_clusters": ([P, P, u64, P, u32, P, P, u64, P, P], i32),
@@ -397,6 +398,25 @@ class HoughContext:
                                             _stream(stream), C.byref(g)), self._h, "hough_graph_capture")
         return HoughGraph(self, g, (hits, acc, peaks, peak_offsets, rz, rz_offsets))
 
+    def get_tables(self, zl=False):
+        """The tables this context uploaded, read back from the device: O, V
+        as [L, D, K]; Z as [K, L, C] (empty without an rz stage); with zl,
+        also Z + z0_lo as the rz kernel reads it."""
+        s = self.spec
+        L, D, K = s["n_layers"], s["n_d0"], s["n_qpt"]
+        nz = K * L * s["n_cot"] if s["n_z0"] else 0
+        O = np.zeros(L * D * K, np.uint32)
+        V = np.zeros(L * D * K, np.uint8)
+        Z = np.zeros(max(nz, 1), np.int32)
+        Zl = np.zeros(max(nz, 1), np.int32) if zl else None
+        rc = self.lib.hough_get_tables(self._h, O.ctypes.data, V.ctypes.data, O.size,
+                                       Z.ctypes.data if nz else None, nz,
+                                       Zl.ctypes.data if zl else None, nz if zl else 0)
+        _check(rc, self._h, "hough_get_tables")
+        C_ = s["n_cot"] if nz else 0
+        out = (O.reshape(L, D, K), V.reshape(L, D, K), Z[:nz].reshape(K, L, C_))
+        return out + (Zl[:nz].reshape(K, L, C_),) if zl else out
+
     # ---- tuning and timing --------------------------------------------
     def set_tuning(self, **kw):
         t = Tuning()
@@ -430,11 +450,13 @@ class HoughContext:
 
 def gather_events(src, src_off, lens, dst_off, n, dst_layer, dst_phi, dst_z, stream=None):
     """Assemble n events of `src` (DeviceHits) into contiguous destination
-    arrays (device tensors); src_off/lens/dst_off are device int64 tensors."""
+    arrays (device tensors); src_off/lens/dst_off are device int64 tensors.
+    Nothing is written past the destination tensors' length."""
     lib = load_library()
+    cap = int(min(dst_layer.numel(), dst_phi.numel(), dst_z.numel() if dst_z is not None else 1 << 62))
     rc = lib.hough_gather_events(_ptr(src.layer), _ptr(src.phi), _ptr(src.z) if dst_z is not None else None,
                                  _ptr(src_off), _ptr(lens), _ptr(dst_off), n, _ptr(dst_layer),
-                                 _ptr(dst_phi), _ptr(dst_z), _stream(stream))
+                                 _ptr(dst_phi), _ptr(dst_z), cap, _stream(stream))
     _check(rc, what="hough_gather_events")
 
 

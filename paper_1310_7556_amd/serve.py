@@ -7,9 +7,9 @@ micro-batch, which runs the whole path (assembly, vote, peaks, rz) on that
 slot's stream while other slots' micro-batches run on theirs.  Accumulators
 and peak/rz buffers live on the device for the life of the server, so a
 request never pays an allocation.  The paper motivates keeping data
-resident on the accelerator across frames (Section 5.2, data persistence on
+resident on the accelerator across frames (Section 6.2, data persistence on
 the coprocessor) and notes that small events cost a fixed overhead (the
-small-event plateau of Section 6); batching arrivals removes that overhead.
+small-event plateau of Section 7); batching arrivals removes that overhead.
 
 The scheduler is plain Python and backend-agnostic, so its policy (FIFO
 order, budget, slot reuse, latency bookkeeping) is tested on the CPU with a
@@ -41,9 +41,11 @@ class Scheduler:
     A slot holds one micro-batch at a time.  When a slot is free,
     next_batch() takes waiting requests in arrival order while the batch has
     at most max_batch events and max_batch_hits hits and the bytes of all
-    in-flight requests stay within budget_bytes.  A request that alone
-    exceeds a limit is admitted alone when nothing else is in flight, so the
-    queue cannot stall."""
+    in-flight requests stay within budget_bytes.  max_batch_hits is also the
+    slots' hit capacity: a request with more hits can never be served and is
+    refused when it arrives (ValueError).  A request whose bytes alone exceed
+    the budget is admitted alone when nothing else is in flight, so the queue
+    cannot stall."""
 
     def __init__(self, n_slots, max_batch, max_batch_hits, budget_bytes):
         self.queue = collections.deque()
@@ -55,6 +57,9 @@ class Scheduler:
         self.batches = {}
 
     def arrive(self, req):
+        if req.n_hits > self.max_batch_hits:
+            raise ValueError(f"request {req.rid}: {req.n_hits} hits exceed the slot capacity of "
+                             f"{self.max_batch_hits} hits")
         self.queue.append(req)
 
     @property
@@ -75,7 +80,7 @@ class Scheduler:
             batch.append(self.queue.popleft())
             hits += r.n_hits
             nbytes += r.nbytes
-            if alone and (r.n_hits > self.max_batch_hits or r.nbytes > self.budget):
+            if alone and r.nbytes > self.budget:
                 break
         if not batch:
             return None, []
@@ -247,6 +252,10 @@ class GpuBackend:
         ih[2, 0] = 0
         np.cumsum(lens, out=ih[2, 1:n + 1])
         total = int(ih[2, n])
+        if total > sl["layer"].numel():
+            # checked before anything is copied: the slot's arrays hold max_batch_hits
+            raise ValueError(f"micro-batch of {total} hits exceeds the slot capacity of "
+                             f"{sl['layer'].numel()} hits")
         s = sl["stream"]
         with torch.cuda.stream(s):
             sl["idx"].copy_(sl["idx_host"], non_blocking=True)
@@ -312,11 +321,15 @@ def make_requests(pool, rate_hz, n, arrivals, device_bytes):
     return reqs
 
 
-def bench_serving(H, torch, log=print, rates=(1000, 2000, 5000, 10000, 20000, 50000, 100000),
-                  seconds=1.0, max_events=5000, plain_events=1500, pool_events=64, n_slots=4,
-                  max_batch=16, staged=True):
+def bench_serving(H, torch, log=print, rates=(250, 500, 1000, 2000, 5000, 10000, 20000, 50000, 100000),
+                  modes=("staged", "h2d"), seconds=1.0, max_events=4000, plain_events=1000, pool_events=64,
+                  n_slots=4, max_batch=16):
     """Latency/throughput sweep of the serving workload: continuous batching
-    vs the plain one-event-per-launch FIFO path on the same arrival traces."""
+    vs the plain one-event-per-launch FIFO path on the same arrival traces,
+    for each mode: "staged" (the event pool resident on the device, a
+    micro-batch assembled by the gather kernel) and "h2d" (the pool in pinned
+    host memory, each micro-batch copied host-to-device asynchronously on its
+    slot's stream)."""
     import synth
     name = "c5_serving"
     spec = synth.grid_spec(name)
@@ -333,27 +346,38 @@ def bench_serving(H, torch, log=print, rates=(1000, 2000, 5000, 10000, 20000, 50
     max_hits = int(max(sizes.max(), min(sizes.sum(), max_batch * np.mean(sizes) * 2)))
     out = dict(workload=f"{name}: Poisson arrivals, pool of {pool_events} events "
                         f"(mean {sizes.mean():.0f} hits, max {sizes.max()}), 512x512 + rz, "
-                        f"rz_max_candidates {cap}", hits_on_device=staged, budget_bytes=budget,
-               slots=n_slots, max_batch=max_batch, rates=[])
+                        f"rz_max_candidates {cap}", budget_bytes=budget,
+               slots=n_slots, max_batch=max_batch, modes={})
     clock = WallClock()
-    cb = GpuBackend(H, torch, spec, pool, n_slots, max_batch, max_hits, clock, staged=staged)
-    plain = GpuBackend(H, torch, spec, pool, 1, 1, int(sizes.max()), clock, staged=staged)
-    for rate in rates:
-        n = int(min(max_events, max(500, rate * seconds)))
-        arr = synth.arrival_times(name, rate, n)
-        row = dict(rate_hz=rate)
-        for label, be, slots, mb, nreq in (("batched", cb, n_slots, max_batch, n),
-                                            ("plain", plain, 1, 1, min(n, plain_events))):
-            reqs = make_requests(pool, rate, nreq, arr, device_bytes)
-            sched = Scheduler(slots, mb, max_hits if mb > 1 else int(sizes.max()), budget)
-            be.start()
-            t_start = clock.now()
-            for r in reqs:
-                r.arrival += t_start
-            run_trace(reqs, sched, be, clock)
-            row[label] = latency_stats(reqs)
-        log(f"serving {rate}/s: batched p50 {row['batched']['p50_ms']:.2f} ms p99 "
-            f"{row['batched']['p99_ms']:.2f} ms {row['batched']['events_per_s']:.0f} ev/s | plain p50 "
-            f"{row['plain']['p50_ms']:.2f} p99 {row['plain']['p99_ms']:.2f} {row['plain']['events_per_s']:.0f} ev/s")
-        out["rates"].append(row)
+    for mode in modes:
+        staged = mode == "staged"
+        cb = GpuBackend(H, torch, spec, pool, n_slots, max_batch, max_hits, clock, staged=staged)
+        plain = GpuBackend(H, torch, spec, pool, 1, 1, int(sizes.max()), clock, staged=staged)
+        res = dict(hits_on_device=staged,
+                   description=("event pool resident in HBM, micro-batches assembled on the device" if staged
+                                else "event pool in pinned host memory, each micro-batch copied host to "
+                                     "device asynchronously on its slot's stream"),
+                   rates=[])
+        for rate in rates:
+            n = int(min(max_events, max(500, rate * seconds)))
+            arr = synth.arrival_times(name, rate, n)
+            row = dict(rate_hz=rate)
+            for label, be, slots, mb, nreq in (("batched", cb, n_slots, max_batch, n),
+                                                ("plain", plain, 1, 1, min(n, plain_events))):
+                reqs = make_requests(pool, rate, nreq, arr, device_bytes)
+                sched = Scheduler(slots, mb, max_hits if mb > 1 else int(sizes.max()), budget)
+                be.start()
+                t_start = clock.now()
+                for r in reqs:
+                    r.arrival += t_start
+                run_trace(reqs, sched, be, clock)
+                row[label] = latency_stats(reqs)
+            log(f"serving [{mode}] {rate}/s: batched p50 {row['batched']['p50_ms']:.2f} ms p99 "
+                f"{row['batched']['p99_ms']:.2f} ms {row['batched']['events_per_s']:.0f} ev/s | plain p50 "
+                f"{row['plain']['p50_ms']:.2f} p99 {row['plain']['p99_ms']:.2f} "
+                f"{row['plain']['events_per_s']:.0f} ev/s")
+            res["rates"].append(row)
+        out["modes"][mode] = res
+        del cb, plain
+        torch.cuda.empty_cache()
     return out

@@ -185,6 +185,13 @@ def device_name(torch, device=0):
     return f"{p.name}/{arch}/{p.multi_processor_count}cu".replace("|", "/")
 
 
+def cached(spec, n_events, n_hits, device=0):
+    """The cached tuning of this workload shape on the current device, or
+    None when the cache has no entry for it."""
+    import torch
+    return lookup(workload_key(spec, n_events, n_hits, device_name(torch, device)))
+
+
 def tune_workload(name, n_events=None, reps=3, cache=CACHE, log=print):
     """Tune the named synthetic workload (see synth.CONFIGS) and cache the
     result; returns (key, tuning, report)."""

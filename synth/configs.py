@@ -1,6 +1,6 @@
 """The five benchmark workloads: detector, track populations and grid specs.
 
-The paper's own study uses a transverse-plane toy Monte Carlo (Section 3,
+The paper's own study uses a transverse-plane toy Monte Carlo (Section 4,
 "Hough Transform Algorithm", the paragraph on the simulated detector); the
 workloads below are synthetic stand-ins of the same kind with a 10-layer
 barrel, a 3.8 T field and uint32 fixed-point azimuth.
@@ -14,7 +14,7 @@ B_TESLA = 3.8
 Z_ACCEPT_MM = 1200.0
 
 
-# The paper's own toy detector (Section 3): 10 evenly spaced layers out to
+# The paper's own toy detector (Section 4): 10 evenly spaced layers out to
 # 1.1 m (read as r = 11 i cm), 0.4 mm hit resolution.
 PAPER_R_MM = tuple(110.0 * i for i in range(1, 11))
 

@@ -293,8 +293,11 @@ def test_peak_and_rz_capacity_overflow(H):
     (dict(rz_counter_bits=4, rz_waves_per_cu=16), dict(n_phi=4, n_qpt=8, n_cot=70)),  # > 192 members: slow path
     (dict(rz_counter_bits=8), {}),
     (dict(rz_counter_bits=16), {}),
-    (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),      # > 512 members: slow path
-    (dict(rz_counter_bits=16), dict(n_phi=2, n_qpt=4, n_cot=9)),      # > 1024 members: slow path
+    # up to about 3000 members per cell: within the 8-bit form's 4096-member
+    # list (counts past 255 are caught as overflows and redone exactly)
+    (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),
+    # up to about 6000 members per cell: past every member list, so the slow path
+    (dict(rz_counter_bits=16), dict(n_phi=2, n_qpt=4, n_cot=9)),
     (None, dict(z0_lo_um=-2147483000, z0_hi_um=2147483000, n_z0=64)),  # general kernel
 ])
 def test_rz_kernel_variants(H, tuning, kw):
@@ -379,11 +382,14 @@ def test_hit_permutation_and_repeat_determinism(H):
         np.testing.assert_array_equal(H.rz_numpy(a["rz"], a["roff"]), H.rz_numpy(x["rz"], x["roff"]))
 
 
-def test_graph_replays_match_eager(H):
+def test_graph_replays_match_oracle_and_eager(H):
     import torch
     spec = small_spec(rz_max_candidates=50)
     batch = ragged_batch()
     eager = run_gpu(H, spec, batch)
+    tab = oracle.Tables(spec)
+    want = [oracle.run_event(tab, *(lambda ev: (ev.layer, ev.phi, ev.z))(batch.event(e)))
+            for e in range(batch.n_events)]
     ctx = H.HoughContext(spec, max_events=batch.n_events, max_hits=batch.n_hits)
     hits = H.DeviceHits.from_batch(batch)
     acc = ctx.new_acc(batch.n_events)
@@ -403,6 +409,10 @@ def test_graph_replays_match_eager(H):
         np.testing.assert_array_equal(H.acc_numpy(acc), H.acc_numpy(eager["acc"]), err_msg=f"replay {rep}")
         np.testing.assert_array_equal(H.peaks_numpy(pk, poff), H.peaks_numpy(eager["pk"], eager["poff"]))
         np.testing.assert_array_equal(H.rz_numpy(rz, roff), H.rz_numpy(eager["rz"], eager["roff"]))
+        for e, (A, opk, orz) in enumerate(want):
+            np.testing.assert_array_equal(H.acc_numpy(acc[e:e + 1])[0], A, err_msg=f"replay {rep}, event {e}")
+            np.testing.assert_array_equal(H.peaks_numpy(pk, poff, e), opk.astype(H.PEAK_DTYPE))
+            np.testing.assert_array_equal(H.rz_numpy(rz, roff, e), orz.astype(H.RZ_DTYPE))
         # eager work on the same context between replays
         run_gpu(H, spec, batch)
     g.close()
@@ -421,3 +431,36 @@ def test_limits_and_bad_arguments_raise(H):
         ctx.set_tuning(vote_algo=5)
     with pytest.raises(H.HoughError):
         H.HoughContext(dict(spec, n_phi=48))
+
+
+@pytest.mark.parametrize("name", list(synth.CONFIGS))
+def test_device_tables_match_oracle(H, name):
+    """The tables a context uploaded, read back from the device, equal the
+    oracle's independently built ones; the rz kernel's (Z + z0_lo) copy
+    equals Z + z0_lo."""
+    spec = synth.grid_spec(name)
+    ctx = H.HoughContext(spec, max_events=1, max_hits=16)
+    tab = oracle.Tables(spec)
+    if spec["n_z0"]:
+        O, V, Z, Zl = ctx.get_tables(zl=True)
+        np.testing.assert_array_equal(Zl.astype(np.int64), tab.Z.astype(np.int64) + spec["z0_lo_um"])
+    else:
+        O, V, Z = ctx.get_tables()
+        with pytest.raises(H.HoughError):
+            ctx.get_tables(zl=True)
+    np.testing.assert_array_equal(O, tab.O)
+    np.testing.assert_array_equal(V, tab.V)
+    np.testing.assert_array_equal(Z, tab.Z)
+
+
+def test_cluster_fit_without_bucket_index_is_refused(H):
+    """A context made without an rz grid and without max_peaks keeps no
+    (layer, azimuth bucket) index: the fit refuses before launching."""
+    spec = synth.grid_spec("c1_single_100trk")
+    batch = synth.gen_config("c1_single_100trk")
+    ctx = H.HoughContext(spec, max_events=1, max_hits=batch.n_hits)
+    hits = H.DeviceHits.from_batch(batch)
+    pk, poff = ctx.new_peaks(16), ctx.new_offsets(1)
+    cl, coff = ctx.new_clusters(16), ctx.new_offsets(1)
+    with pytest.raises(H.HoughError, match="invalid argument"):
+        ctx.cluster_fit(hits, pk, poff, cl, coff, peak_capacity=16, capacity=16)

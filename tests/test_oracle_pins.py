@@ -3,7 +3,7 @@
 Each test fixes part of the oracle against the mathematics or the paper:
 continuous-angle brute force through an independent trajectory construction,
 closed forms, the vote-count invariant, bin-centre tracks, missing-hit
-tolerance (Section 3: the transform tolerates missing hits), exact rotation
+tolerance (Section 4: the transform tolerates missing hits), exact rotation
 covariance, hit-order independence, a library maximum filter, and a dense
 argmax of the rz grid.
 """

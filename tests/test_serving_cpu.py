@@ -59,6 +59,12 @@ def test_oversized_request_is_admitted_alone():
     assert [r.done for r in rs] == [1.0, 2.0]
 
 
+def test_request_larger_than_a_slot_is_refused():
+    rs = reqs([0.0, 0.0], n_hits=800)
+    with pytest.raises(ValueError):
+        run(rs, slots=2, max_batch=8, max_hits=700)
+
+
 def test_max_batch_hits_splits_batches():
     rs = reqs([0.0] * 5, n_hits=300)
     be = run(rs, slots=1, max_batch=8, max_hits=700)

@@ -1,10 +1,12 @@
 """Serving on the GPU: every request completes, and a request's accumulator,
 peaks and rz records are identical whether it is served alone or inside a
-Poisson mix of concurrently running micro-batches (exact equality: the
-results are integers)."""
+Poisson mix of concurrently running micro-batches, and equal to the CPU
+oracle's (exact equality: the results are integers).  Both the device-staged
+pool and async host-to-device copies from pinned memory are covered."""
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +38,7 @@ def test_results_alone_equal_results_in_the_mix(staged):
     assert st["n"] == 120 and all(r.done >= r.arrival for r in reqs)
     assert max(len(b) for b in [[r for r in reqs if r.admitted == t] for t in {r.admitted for r in reqs}]) > 1
     assert set(be.kept) == set(keep)
+    tab = oracle.Tables(spec)
     for rid in keep:
         e = reqs[rid].event
         ctx = H.HoughContext(spec, max_events=1, max_hits=int(sizes[e]))
@@ -48,3 +51,9 @@ def test_results_alone_equal_results_in_the_mix(staged):
         np.testing.assert_array_equal(acc_m, H.acc_numpy(acc)[0])
         np.testing.assert_array_equal(pk_m, H.peaks_numpy(pk, poff))
         np.testing.assert_array_equal(rz_m, H.rz_numpy(rz, roff))
+        # and both equal the oracle's results for that event
+        ev = pool.event(e)
+        A, opk, orz = oracle.run_event(tab, ev.layer, ev.phi, ev.z)
+        np.testing.assert_array_equal(acc_m, A, err_msg=f"request {rid}: accumulator")
+        np.testing.assert_array_equal(pk_m, opk.astype(H.PEAK_DTYPE), err_msg=f"request {rid}: peaks")
+        np.testing.assert_array_equal(rz_m, orz.astype(H.RZ_DTYPE), err_msg=f"request {rid}: rz")
