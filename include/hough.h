@@ -220,6 +220,22 @@ int hough_peaks(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events,
                 hough_peak *peaks, uint64_t capacity, uint64_t *event_peak_offsets,
                 void *stream);
 
+/* hough_peaks for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same results from the same kernels, but the peak search's scratch
+ * (per-tile peak counts, their prefix and the scan's block sums) lives in
+ * one static device array of 8 MiB per GPU, held until the process ends,
+ * instead of the context's buffers.  The call itself allocates nothing
+ * (host or device) and records no per-kernel timing.  A call needing more
+ * than 8 MiB (about 12 bytes per peak tile, a tile being peak_rows rows of
+ * one d0 plane of one event: some 690,000 tiles) returns HOUGH_ELIMIT, with
+ * the sizes in hough_last_error.  Every noalloc call on one GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (from any context
+ * or stream) race; a call needs nothing from the array's earlier contents. */
+int hough_peaks_noalloc(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events,
+                        hough_peak *peaks, uint64_t capacity, uint64_t *event_peak_offsets,
+                        void *stream);
+
 /* Step 1 in the paper's counting form (the Discussion's A[B[i]] += 1): for
  * every event e, every hit h of e with layer l < n_layers and every
  * reachable row (d, k):

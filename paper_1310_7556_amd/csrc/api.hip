@@ -260,6 +260,9 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     if (err == hipSuccess && rzh) err = hipMemset(c->d_rz_hist, 0, rzh * 4);
     if (err == hipSuccess) err = hipMemset(c->d_counters, 0, 64 * 4);
     if (err == hipSuccess) err = hipDeviceSynchronize();
+    // the static scratch of hough_peaks_noalloc: its address on this device,
+    // looked up once per device (a failure is reported by that call)
+    if (err == hipSuccess) (void)noalloc_scratch_init(device);
     if (err != hipSuccess) {
         free_all(c);
         delete c;
@@ -296,6 +299,32 @@ int hough_peaks(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events, hough_pe
     const hipError_t e = launch_peaks(ctx, acc, n_events, peaks, capacity, event_peak_offsets,
                                       static_cast<hipStream_t>(stream));
     return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peaks");
+}
+
+int hough_peaks_noalloc(hough_ctx *ctx, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
+                        uint64_t capacity, uint64_t *event_peak_offsets, void *stream)
+{
+    if (!ctx || !event_peak_offsets || (n_events && !acc) || (capacity && !peaks)) return HOUGH_EINVAL;
+    if (n_events > ctx->lim.max_events) return HOUGH_ELIMIT;
+    DeviceGuard guard(ctx->device);
+    void *base = noalloc_scratch(ctx->device);
+    if (!base) {
+        const hipError_t e = noalloc_scratch_init(ctx->device);
+        base = noalloc_scratch(ctx->device);
+        if (!base) return device_error(ctx, e, "hough_peaks_noalloc: address of the static scratch");
+    }
+    const uint64_t tiles = peak_items(ctx, n_events, acc);
+    if (n_events && tiles == 0) return device_error(ctx, hipErrorInvalidConfiguration, "hough_peaks_noalloc");
+    const size_t need = peak_scratch_bytes(tiles);
+    if (need > kNoAllocScratchBytes) {
+        ctx->last_error = "hough_peaks_noalloc: " + std::to_string(tiles) + " peak tiles need " +
+                          std::to_string(need) + " bytes of static scratch, more than its " +
+                          std::to_string(kNoAllocScratchBytes);
+        return HOUGH_ELIMIT;
+    }
+    const hipError_t e = launch_peaks(ctx, acc, n_events, peaks, capacity, event_peak_offsets,
+                                      static_cast<hipStream_t>(stream), carve_peak_scratch(base, tiles), false);
+    return e == hipSuccess ? HOUGH_OK : device_error(ctx, e, "hough_peaks_noalloc");
 }
 
 int hough_vote_count(hough_ctx *ctx, const hough_hits *hits, uint32_t *counts, void *stream)

@@ -134,6 +134,15 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
                         const PeakScratch &ps, bool timed = true);
 hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, hough_peak *peaks,
                         uint64_t capacity, uint64_t *event_peak_offsets, hipStream_t s);
+// hough_peaks_noalloc's file-scope device scratch: its byte size, the
+// lookup of its address on a device (once per device, with that device
+// current) and that address (nullptr until looked up).
+extern const size_t kNoAllocScratchBytes;
+hipError_t noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
+// Bytes of peak scratch for n tiles when carved from one buffer, and the carving.
+size_t peak_scratch_bytes(uint64_t n_tiles);
+PeakScratch carve_peak_scratch(void *base, uint64_t n_tiles);
 hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
                      uint64_t peak_capacity, const uint64_t *event_peak_offsets, hough_rz *out,
                      uint64_t capacity, uint64_t *event_rz_offsets, hipStream_t s);

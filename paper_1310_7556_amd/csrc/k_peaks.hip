@@ -9,10 +9,75 @@
 // exclusive scan over tiles in (event, d0, row) order, and a write pass that
 // places each 64-wide wavefront's peaks with ballot + mbcnt prefixes and
 // each workgroup's waves with an LDS prefix.
+#include <mutex>
+
 #include "hough_internal.h"
+
+// Scratch of hough_peaks_noalloc, for callers that cannot allocate device
+// memory: one file-scope array, of which each GPU holds its own copy until
+// the process ends.  In host code its name is only a stand-in for the
+// device symbol; its address on a device comes from hipGetSymbolAddress,
+// looked up once per device (noalloc_scratch_init) and then used for every
+// kernel argument.  Concurrent noalloc calls on one GPU share it and race.
+static __device__ __align__(256) unsigned char scratch[size_t(8) << 20];
 
 namespace hough {
 
+const size_t kNoAllocScratchBytes = size_t(8) << 20;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = p;
+    return e;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+namespace {
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t peak_scratch_bytes(uint64_t n_tiles)
+{
+    const uint64_t nb = scan_blocks(n_tiles);
+    return align256(4 * n_tiles) + align256(8 * (n_tiles + 1)) + align256(8 * nb) + align256(8 * (nb + 1));
+}
+
+PeakScratch carve_peak_scratch(void *base, uint64_t n_tiles)
+{
+    const uint64_t nb = scan_blocks(n_tiles);
+    char *p = static_cast<char *>(base);
+    PeakScratch ps;
+    ps.tile_counts = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * n_tiles);
+    ps.tile_off = reinterpret_cast<uint64_t *>(p);
+    p += align256(8 * (n_tiles + 1));
+    ps.scan_part = reinterpret_cast<uint64_t *>(p);
+    p += align256(8 * nb);
+    ps.scan_off = reinterpret_cast<uint64_t *>(p);
+    ps.scan_blocks_max = nb;
+    return ps;
+}
 
 template <bool WRITE>
 __global__ void __launch_bounds__(256)

@@ -23,7 +23,7 @@ EXPORTED = [
     "hough_set_profiling", "hough_kernel_times", "hough_kernel_times_reset",
     "hough_strerror", "hough_last_error", "hough_device_cus", "hough_gather_events",
     "hough_vote_count", "hough_peaks_count", "hough_peak_clusters",
-    "hough_cluster_fit", "hough_get_tables",
+    "hough_cluster_fit", "hough_get_tables", "hough_peaks_noalloc",
 ]
 
 PEAK_DTYPE = np.dtype([("cell", np.uint32), ("mask", np.uint16), ("popcount", np.uint16)])
@@ -85,6 +85,7 @@ def load_library():
         "hough_destroy": ([P], None),
         "hough_vote": ([P, P, P, P], i32),
         "hough_peaks": ([P, P, u32, P, u64, P, P], i32),
+        "hough_peaks_noalloc": ([P, P, u32, P, u64, P, P], i32),
         "hough_rz_refine": ([P, P, P, u64, P, P, u64, P, P], i32),
         "hough_graph_capture": ([P, P, P, P, u64, P, P, u64, P, P, P], i32),
         "hough_graph_launch": ([P, P], i32),
