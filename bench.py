@@ -54,6 +54,11 @@ VOTE_KERNEL_BYTES = {
     "vote_direct": lambda n_hits, cells: 2 * cells,
     "vote_scan": lambda n_hits, cells: 5 * n_hits,
     "vote_gaps": lambda n_hits, cells: 2 * cells,
+    # rank form: whole events per workgroup read their hits and write their
+    # cells in one kernel; one tile per workgroup reads a bounds table
+    # written by vote_bounds
+    "vote_rank_event": lambda n_hits, cells: 5 * n_hits + 2 * cells,
+    "vote_rank_tile": lambda n_hits, cells: 2 * cells,
 }
 
 
@@ -276,13 +281,14 @@ def bench_batched(H, torch, reps=5):
         stream.synchronize()
         ctx.set_profiling(False)
         times = ctx.kernel_times()
-    vk = next(k for k in ("vote_direct", "vote_gaps", "vote_lds") if k in times)
+    vk = next(k for k in ("vote_rank_event", "vote_rank_tile", "vote_direct", "vote_gaps", "vote_lds") if k in times)
     t_vote = kernel_avg_ms(times, vk) * 1e-3
     vote_bytes = VOTE_KERNEL_BYTES[vk](batch.n_hits, E * ctx.cells)
     gbs = vote_bytes / t_vote / 1e9
     stage_bytes = 5 * batch.n_hits + 2 * E * ctx.cells
     t_stage = sum(kernel_avg_ms(times, k) for k in ("vote_bounds", "vote_direct", "vote_scan", "vote_gaps",
-                                                     "vote_lds", "bucket_layers")
+                                                     "vote_lds", "bucket_layers", "vote_rank_event",
+                                                     "vote_rank_tile")
                   if k in times) * 1e-3
 
     # the per-hit LDS-atomic form of the vote (the paper's recipe), timed once
@@ -458,20 +464,23 @@ def recorded_traffic(name):
     return round(k["bytes_per_launch"]) if source_sha(k["source"]) == k["sha256"] else None
 
 
-# The direct vote decides every (cell, layer) pair with three VALU
-# instructions per 64 decisions (subtract, subtract with borrow, add with
-# carry): its own ALU roof, beside the HBM one.
-DIRECT_VALU_PER_64_DECISIONS = 3
+# Lane operations per (cell, layer) decision of the vote forms that decide
+# every cell: the direct form uses three VALU instructions per 64 decisions
+# (subtract, subtract with borrow, add with carry); the rank form five per
+# 4 x 64 (two subtracts, a three-input bit operation, a shift and a bit-field
+# insert on four byte lanes).  Their ALU roof, beside the HBM one.
+VOTE_LANE_OPS_PER_DECISION = {"vote_direct": 3.0, "vote_rank_event": 1.25, "vote_rank_tile": 1.25}
 
 
 def vote_alu_view(kernel, cells, layers, seconds):
-    """ALU roofline of the direct vote: cells x layers decisions per launch."""
-    if kernel != "vote_direct":
+    """ALU roofline of a deciding vote form: cells x layers decisions per launch."""
+    per = VOTE_LANE_OPS_PER_DECISION.get(kernel)
+    if per is None:
         return None
     decisions = cells * layers
-    ops = decisions * DIRECT_VALU_PER_64_DECISIONS       # lane operations
+    ops = decisions * per                                  # lane operations
     alu_floor = ops / (ALU_PEAK_TOPS * 1e12)
-    return dict(decisions_per_launch=decisions, lane_ops_per_decision=DIRECT_VALU_PER_64_DECISIONS,
+    return dict(decisions_per_launch=decisions, lane_ops_per_decision=per,
                 achieved_tops=round(ops / seconds / 1e12, 3), peak_tops=round(ALU_PEAK_TOPS, 2),
                 frac=round(alu_floor / seconds, 5), alu_floor_ms=round(alu_floor * 1e3, 4),
                 hbm_floor_ms=round(2 * cells / (HBM_PEAK_GBS * 1e9) * 1e3, 4))

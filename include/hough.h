@@ -168,10 +168,16 @@ typedef struct {
     uint32_t vote_wgs_per_cu;       /* persistent vote grid: workgroups per compute unit */
     uint32_t peak_rows;             /* accumulator rows per peak-finding tile */
     uint32_t rz_waves_per_cu;       /* persistent rz grid: waves per compute unit */
-    uint32_t vote_algo;             /* 0 = default (4), 1 = per-hit LDS atomics, 2 = global atomics,
-                                       3 = hit-gap lists, 4 = bucket bounds (direct occupancy) */
+    uint32_t vote_algo;             /* 0 = default (5 where usable, else 4), 1 = per-hit LDS atomics,
+                                       2 = global atomics, 3 = hit-gap lists, 4 = bucket bounds (direct
+                                       occupancy), 5 = bucket bounds in tile rank space, four cells per
+                                       operation (n_phi 256, 512 or 1024; accumulator 8-byte aligned,
+                                       else form 4 is used) */
     uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
     uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 4, 8 or 16 */
+    uint32_t vote_items;            /* vote form 5: 0 = automatic, 1 = a whole event per workgroup (bucket
+                                       bounds found in LDS), 2 = one row tile per workgroup (bounds from a
+                                       table pass over the hits) */
 } hough_tuning;
 
 /* ---- context --------------------------------------------------------- */

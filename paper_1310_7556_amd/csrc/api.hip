@@ -48,7 +48,7 @@ bool dev_alloc(T **p, size_t count)
 
 void free_all(hough_ctx *c)
 {
-    void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
+    void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_rk_info, c->d_rk_sorted, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
                     c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list,
                     c->d_scan_part, c->d_scan_off, c->d_dir_tab, c->d_cl_rank, c->d_cl_part,
@@ -83,9 +83,11 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.vote_wgs_per_cu > 32) return false;
     if (t.peak_rows > 4096) return false;
     if (t.rz_waves_per_cu > kMaxRzWavesPerCu) return false;
-    if (t.vote_algo > 4) return false;
+    if (t.vote_algo > 5) return false;
     if (t.vote_algo == 3 && !hough::gap_vote_usable(c)) return false;
     if (t.vote_algo == 4 && !hough::direct_vote_usable(c)) return false;
+    if (t.vote_algo == 5 && !c->d_rk_info) return false;
+    if (t.vote_items > 2) return false;
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 4 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16)
         return false;
@@ -186,6 +188,9 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = std::min<size_t>(size_t(lds) - 512, 65536);   // headroom for static LDS
     c->max_lds_direct = c->max_lds;
+    // the rank vote may use up to half of a compute unit's LDS (two of its
+    // 512-thread workgroups per compute unit)
+    if (lds > 0) c->max_lds_rank = std::max<size_t>(c->max_lds, std::min<size_t>(size_t(lds) - 512, 81920));
     while ((1u << c->log2_phi) < spec->n_phi) ++c->log2_phi;
     c->shift = 32 - c->log2_phi;
     c->rows = spec->n_d0 * spec->n_qpt;
@@ -223,6 +228,9 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
         if (!ok) Zl.clear();
     }
 
+    std::vector<uint32_t> rk_info, rk_sorted;
+    if (rank_vote_form(*spec)) build_rank_tables(*spec, c->rows, c->shift, O.data(), V.data(), rk_info, rk_sorted);
+
     const uint64_t H = limits->max_hits ? limits->max_hits : 1;
     const uint32_t E = limits->max_events;
     const uint32_t L = spec->n_layers;
@@ -245,7 +253,8 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
               dev_alloc(&c->d_dir_tab, size_t(E) * L * spec->n_phi) &&
               dev_alloc(&c->d_cl_rank, limits->max_peaks) &&
               dev_alloc(&c->d_cl_part, cluster_blocks(limits->max_peaks)) &&
-              dev_alloc(&c->d_cl_part_off, cluster_blocks(limits->max_peaks) + 1);
+              dev_alloc(&c->d_cl_part_off, cluster_blocks(limits->max_peaks) + 1) &&
+              dev_alloc(&c->d_rk_info, rk_info.size()) && dev_alloc(&c->d_rk_sorted, rk_sorted.size());
     if (!ok) {
         free_all(c);
         delete c;
@@ -258,6 +267,10 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     if (err == hipSuccess && !Zl.empty())
         err = hipMemcpy(c->d_Zl, Zl.data(), Zl.size() * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess && rzh) err = hipMemset(c->d_rz_hist, 0, rzh * 4);
+    if (err == hipSuccess && !rk_info.empty())
+        err = hipMemcpy(c->d_rk_info, rk_info.data(), rk_info.size() * 4, hipMemcpyHostToDevice);
+    if (err == hipSuccess && !rk_sorted.empty())
+        err = hipMemcpy(c->d_rk_sorted, rk_sorted.data(), rk_sorted.size() * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess) err = hipMemset(c->d_counters, 0, 64 * 4);
     if (err == hipSuccess) err = hipDeviceSynchronize();
     // the static scratch of hough_peaks_noalloc: its address on this device,

@@ -27,6 +27,12 @@ constexpr uint32_t kMaxBucketBits = 12;
 // read a whole tile's worth of offsets past the last row.
 constexpr size_t kOPad = 64;
 
+// Rank form of the vote: rows per tile (ranks fit a byte), workgroup size
+// and the stride of a tile's sorted fine offsets (128 values + padding).
+constexpr uint32_t kRankTileRows = 128;
+constexpr uint32_t kRankThreads = 512;
+constexpr uint32_t kRankSortStride = 132;
+
 struct KernelTimer {
     const char *name;
     hipEvent_t start, stop;
@@ -85,7 +91,10 @@ struct hough_ctx {
     uint64_t *d_scan_off = nullptr;    // [scan_blocks_max + 1] their exclusive prefix
     uint64_t scan_blocks_max = 0;
     uint2 *d_dir_tab = nullptr;        // [max_events][L][n_phi] direct vote: per-bucket {lo, span}
+    uint32_t *d_rk_info = nullptr;     // [rows][16] rank vote: rank | J << 8 | unreachable << 31
+    uint32_t *d_rk_sorted = nullptr;   // [tiles][L][kRankSortStride] rank vote: sorted fine offsets
     size_t max_lds_direct = 65536;     // LDS budget of the direct vote's table staging
+    size_t max_lds_rank = 65536;       // LDS budget of the rank vote (two workgroups per compute unit)
     uint64_t n_peak_tiles = 0;
     uint32_t *d_cl_rank = nullptr;     // [max_peaks] plateau clusters: cluster index of each root
     uint32_t *d_cl_part = nullptr;     // [cluster blocks] roots per block of the peak list
@@ -153,6 +162,13 @@ uint32_t vote_rows(const hough_ctx *c);
 hipError_t launch_vote_gaps(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
 hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
 bool direct_vote_usable(const hough_ctx *c);
+hipError_t launch_vote_bounds(hough_ctx *c, const hough_hits *h, hipStream_t s);
+// rank form: spec support, host tables (built at create), usability, launch
+bool rank_vote_form(const hough_grid_spec &g);
+void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, const uint32_t *O, const uint8_t *V,
+                       std::vector<uint32_t> &info, std::vector<uint32_t> &sorted);
+bool rank_vote_usable(const hough_ctx *c, const uint16_t *acc);
+hipError_t launch_vote_rank(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
 uint32_t gap_rows(const hough_ctx *c);
 bool gap_vote_usable(const hough_ctx *c);
 uint32_t rz_blocks(const hough_ctx *c);

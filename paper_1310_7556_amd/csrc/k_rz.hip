@@ -306,11 +306,18 @@ __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
     }
 }
 
-// LDS layout of the fast kernel, in dwords.
+// LDS layout of the fast kernel, in dwords: counters, the layer windows,
+// the pass boundary table, then two member lists (all members of the
+// candidate; those of the current pass), each z values then layer bytes for
+// mcap members plus up to 7 padding ones, 16-byte aligned.
+__host__ __device__ inline uint32_t rz_list_z_dwords(uint32_t mcap) { return (mcap + 8 + 3) & ~3u; }
+__host__ __device__ inline uint32_t rz_list_dwords(uint32_t mcap)
+{
+    return rz_list_z_dwords(mcap) + ((((mcap + 8 + 3) / 4) + 3) & ~3u);
+}
 __host__ __device__ inline uint32_t rz_fast_lds_dwords(uint32_t hw, uint32_t mcap)
 {
-    // member z and layer arrays hold mcap members plus up to 7 padding ones
-    return hw * 64 + 96 + 32 + (mcap + 8) + (mcap + 8 + 3) / 4;
+    return hw * 64 + 96 + 32 + 2 * rz_list_dwords(mcap);
 }
 
 // SHIFT: the bin multiply needs its extra right shift (bs > 0).
@@ -327,9 +334,11 @@ k_rz_vote_fast(RzParams P)
     const uint32_t lane = threadIdx.x;
     uint32_t *hist = lds;                            // [hw][64] lane-private packed counters
     uint32_t *lay = hist + P.hw * 64;                // [5][16] per-layer windows
-    uint32_t *loff = lay + 96;                       // [L + 1] member offsets per layer
-    int32_t *mz = reinterpret_cast<int32_t *>(loff + 32);    // [mcap] member z
-    uint8_t *ml = reinterpret_cast<uint8_t *>(mz + P.mcap + 8);  // [mcap + 8] member layer
+    int32_t *tb = reinterpret_cast<int32_t *>(lay + 96);     // [2][16] pass boundaries per layer
+    int32_t *mz = tb + 32;                                   // [mcap] member z
+    uint8_t *ml = reinterpret_cast<uint8_t *>(mz + rz_list_z_dwords(P.mcap));   // member layer
+    int32_t *mzc = mz + rz_list_dwords(P.mcap);              // this pass's members: z
+    uint8_t *mlc = reinterpret_cast<uint8_t *>(mzc + rz_list_z_dwords(P.mcap));  // and layer
     // 16-bit counters cannot overflow below FIELD members; 4- and 8-bit
     // counters detect an overflow instead and send the candidate to the
     // exact slow path
@@ -367,6 +376,13 @@ k_rz_vote_fast(RzParams P)
             for (uint32_t l = 0; l + 1 < kMaxLayers; ++l) zr[l] = uint32_t(zl0[size_t(min(l, nl - 1)) * P.n_cot]);
             zr[kMaxLayers - 1] = 0u;
         }
+        // the first pass's boundary values: lanes 0..15 read Zl at its first
+        // cot bin, lanes 16..31 at its last, one layer each (clamped index)
+        auto boundary = [&](uint32_t jp) {
+            const uint32_t jb = lane < 16 ? jp : min(jp + 63u, P.n_cot - 1);
+            return zrow[size_t(min(lane & 15u, nl - 1)) * P.n_cot + min(jb, P.n_cot - 1)];
+        };
+        int32_t tbv = boundary(0);
 
         // 1a. lane l < L: the azimuth-bucket window of layer l (one or two
         // ranges of the (layer, bucket)-sorted hits, two when it wraps)
@@ -434,15 +450,6 @@ k_rz_vote_fast(RzParams P)
             }
             nm += __popcll(bal);
         }
-        // pad the member list to a multiple of 4 with members that never
-        // vote: layer 15 is unused (n_layers < 16 on this path), so its
-        // (Z + z0_lo) register is 0, and z = 0xFFFFFFFF is then out of range
-        // for every cot bin
-        const uint32_t np4 = (nm + 3u) & ~3u;
-        if (nm <= lim && lane < np4 - nm) {
-            mz[nm + lane] = -1;
-            ml[nm + lane] = uint8_t(kMaxLayers - 1);
-        }
         __syncthreads();
 
         uint32_t best_c = 0, best_j = lane, best_b = 0;
@@ -453,6 +460,47 @@ k_rz_vote_fast(RzParams P)
             for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 64) {
                 const uint32_t j = j0 + lane;
                 const bool jv = j < P.n_cot;
+                // Members of this pass.  (Z + z0_lo) is monotone in the cot
+                // bin (cot_j is linear in j, the arc length is positive and
+                // rounding keeps the order), so over the pass's cot bins
+                // [ja, jb] it lies between its values at ja and jb, and a
+                // member can vote in range only if min <= z and z - max <
+                // span; every vote of the others would go to the trash
+                // counter, so they are left out of the pass (the result is
+                // unchanged).
+                if (lane < 32) tb[lane] = tbv;
+                __syncthreads();
+                tbv = boundary(j0 + 64);             // next pass's, in flight meanwhile
+                uint32_t nq = 0;
+                for (uint32_t c0 = 0; c0 < nm; c0 += 64) {
+                    const uint32_t m = c0 + lane;
+                    bool act = false;
+                    int32_t zm = 0;
+                    uint32_t lm = 0;
+                    if (m < nm) {
+                        zm = mz[m];
+                        lm = ml[m];
+                        const int32_t za = tb[lm], zb = tb[16 + lm];
+                        act = zm >= min(za, zb) && int64_t(zm) - int64_t(max(za, zb)) < int64_t(P.span);
+                    }
+                    const uint64_t bal = __ballot(act);
+                    const uint32_t pos = nq + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (act) {
+                        mzc[pos] = zm;
+                        mlc[pos] = uint8_t(lm);
+                    }
+                    nq += __popcll(bal);
+                }
+                // pad to a multiple of 4 with members that never vote: layer
+                // 15 is unused (n_layers < 16 on this path), so its (Z +
+                // z0_lo) register is 0, and z = 0xFFFFFFFF is then out of
+                // range for every cot bin
+                const uint32_t np4 = (nq + 3u) & ~3u;
+                if (lane < np4 - nq) {
+                    mzc[nq + lane] = -1;
+                    mlc[nq + lane] = uint8_t(kMaxLayers - 1);
+                }
+                __syncthreads();
                 // next pass's rows (after the last pass they are loaded and
                 // not used: the index is clamped, so the loads stay in bounds)
                 const int32_t *zln = zrow + min(j + 64, P.n_cot - 1);
@@ -470,8 +518,8 @@ k_rz_vote_fast(RzParams P)
                 // packed counter atomic and the running maximum of the signed
                 // key (count - 1) * 2^16 - b over in-range votes (largest
                 // count wins, ties to the smallest bin)
-                const uint4 *mz4 = reinterpret_cast<const uint4 *>(mz);
-                const uint32_t *ml4 = reinterpret_cast<const uint32_t *>(ml);
+                const uint4 *mz4 = reinterpret_cast<const uint4 *>(mzc);
+                const uint32_t *ml4 = reinterpret_cast<const uint32_t *>(mlc);
                 // this lane's counter column (row stride 64 dwords)
                 uint32_t *col = hist + lane;
                 int32_t run = INT32_MIN;
@@ -524,12 +572,14 @@ k_rz_vote_fast(RzParams P)
                 // clear all counters, 16 bytes per lane per store; a store
                 // covers other lanes' columns, so every lane's counting must
                 // be finished first and the clear finished before the next
-                // cot bins are counted
-                __syncthreads();
-                uint4 *h4 = reinterpret_cast<uint4 *>(hist);
-                const uint32_t n4 = P.hw * 16;
+                // cot bins are counted (nothing to clear after an empty pass)
+                if (np4) {
+                    __syncthreads();
+                    uint4 *h4 = reinterpret_cast<uint4 *>(hist);
+                    const uint32_t n4 = P.hw * 16;
 #pragma unroll 4
-                for (uint32_t i = lane; i < n4; i += 64) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+                    for (uint32_t i = lane; i < n4; i += 64) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+                }
                 __syncthreads();
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
             }
@@ -691,12 +741,12 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     const uint32_t blocks = c->tun.rz_waves_per_cu ? rz_blocks(c) : uint32_t(c->n_cu) * (bits == 4 ? 16u : 8u);
     // counter dwords per lane: bins 0 .. n_z0 - 1 plus the trash bin n_z0
     const uint32_t hw = g.n_z0 / (32 / bits) + 1;
-    // member list: 192 with 4-bit counters (16 waves of counters and list
-    // fit 160 KB); otherwise as many as fit the LDS budget, up to 4096: a
+    // member lists: 112 with 4-bit counters (16 waves of counters and two
+    // lists fit 160 KB); otherwise as many as fit the LDS budget, up to 4096: a
     // candidate with more members takes the slow path, which is far slower
     // (it walks every hit of the cell's windows per cot bin), so dense
     // events need the long list more than occupancy
-    uint32_t mcap = bits == 4 ? 192 : 256;
+    uint32_t mcap = bits == 4 ? 112 : 256;
     if (bits != 4) {
         mcap = 4096;
         while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;

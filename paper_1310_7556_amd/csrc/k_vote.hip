@@ -193,7 +193,9 @@ uint32_t vote_rows(const hough_ctx *c)
 hipError_t launch_vote(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s)
 {
     if (h->n_events == 0) return hipSuccess;
-    if ((c->tun.vote_algo == 0 || c->tun.vote_algo == 4) && direct_vote_usable(c))
+    if ((c->tun.vote_algo == 0 || c->tun.vote_algo == 5) && rank_vote_usable(c, acc))
+        return launch_vote_rank(c, h, acc, s);
+    if ((c->tun.vote_algo == 0 || c->tun.vote_algo == 4 || c->tun.vote_algo == 5) && direct_vote_usable(c))
         return launch_vote_direct(c, h, acc, s);
     if ((c->tun.vote_algo == 0 || c->tun.vote_algo == 3) && gap_vote_usable(c)) return launch_vote_gaps(c, h, acc, s);
     return launch_vote_hits<false>(c, h, acc, s);

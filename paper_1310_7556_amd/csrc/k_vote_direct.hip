@@ -279,7 +279,7 @@ bool direct_vote_usable(const hough_ctx *c)
     return c->d_dir_tab != nullptr && size_t(c->spec.n_phi) * 8 <= c->max_lds;
 }
 
-hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s)
+hipError_t launch_vote_bounds(hough_ctx *c, const hough_hits *h, hipStream_t s)
 {
     const uint32_t E = h->n_events;
     const uint32_t group = uint32_t(std::min<size_t>(c->spec.n_layers, c->max_lds / (size_t(c->spec.n_phi) * 8)));
@@ -290,7 +290,14 @@ hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, 
                        h->event_offsets, h->n_hits, c->spec.n_layers, c->spec.n_phi, c->log2_phi, c->shift, group,
                        vec, c->d_dir_tab);
     prof_end(c, s, &t);
-    hipError_t err = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s)
+{
+    const uint32_t E = h->n_events;
+    KernelTimer t;
+    hipError_t err = launch_vote_bounds(c, h, s);
     if (err != hipSuccess) return err;
     uint32_t R = direct_rows(c);
     if (!c->tun.vote_rows) {

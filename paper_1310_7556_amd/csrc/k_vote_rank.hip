@@ -1,0 +1,365 @@
+// Step 1 of the transform (Section 4, first step; the Discussion's
+// A[B[i]] += 1 in its layer-mask form) in a rank form that decides four
+// (cell, layer) pairs with one 32-bit operation.  The default vote.
+//
+// Bin p of row r (offset o = J W + F, W = 2^32 / n_phi) holds a hit of layer
+// l unless bucket j = J + p is empty at F: F in [lo_j, hi_j], with lo_j the
+// largest fine offset of bucket j plus one (0 when the bucket is empty) and
+// hi_j the smallest fine offset of bucket j + 1 (W - 1 when empty); this is
+// the bucket-bounds form of k_vote_direct.hip.  Within a tile of at most 128
+// consecutive rows only the order of the rows' fine offsets matters: with
+// the tile's F values sorted, F_r in [lo, hi] iff rank_r in [a, b), where
+// rank_r = #{F < F_r}, a = #{F < lo} and b = #{F <= hi}.  Rank, a and the
+// span b - a all fit a byte (at most 128), so a word holds the (a, span) of
+// four consecutive buckets, and with R = 0x80 + rank in every byte
+//     x = R - a,  y = x - span
+// never borrow across bytes (x in [0, 255], y >= rank); bucket byte k is
+// empty iff bit 7 of x is set and bit 7 of y is clear.  Per row and layer,
+// rank and J are wave-uniform scalars from a static table; a lane owns
+// groups of four consecutive cells and keeps the (a, span) words of its
+// buckets in registers while the row's J is unchanged (J moves by at most a
+// fraction of a bin per row).  Layer bits are shifted into byte-wide masks
+// and interleaved into uint16 cells with byte permutes.  Bit-identical to
+// the per-hit vote; no atomics outside the bucket bounds, no divergence.
+//
+// Items are (event, run of 128-row tiles).  With BOUNDS an item covers a
+// whole event and first finds the bucket bounds from the event's hits in
+// LDS (the hits are read once, no table goes through HBM); otherwise the
+// bounds come from k_vote_bounds' per-event table, for single large events
+// split into many items.
+#include <algorithm>
+#include <vector>
+
+#include "hough_internal.h"
+
+namespace hough {
+
+namespace {
+
+// Calls f(layer, phi) for every hit of [b, end); with `vec` (layer 4-byte
+// and phi 16-byte aligned) the aligned middle is read four hits per load.
+template <class F>
+__device__ __forceinline__ void rank_event_hits(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
+                                                uint64_t b, uint64_t end, uint32_t t, uint32_t nt, bool vec, F &&f)
+{
+    uint64_t tail = b;
+    if (vec) {
+        const uint64_t a = min((b + 3) & ~uint64_t(3), end);
+        if (t < a - b) f(uint32_t(layer[b + t]), phi[b + t]);
+        const uint64_t nq = (end - a) >> 2;
+        const uint32_t *l4 = reinterpret_cast<const uint32_t *>(layer + a);
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(phi + a);
+        for (uint64_t q = t; q < nq; q += nt) {
+            const uint32_t lw = l4[q];
+            const uint4 pw = p4[q];
+            f(lw & 0xFFu, pw.x);
+            f((lw >> 8) & 0xFFu, pw.y);
+            f((lw >> 16) & 0xFFu, pw.z);
+            f(lw >> 24, pw.w);
+        }
+        tail = a + (nq << 2);
+    }
+    for (uint64_t i = tail + t; i < end; i += nt) f(uint32_t(layer[i]), phi[i]);
+}
+
+// #{s[k] < x} over a tile's sorted fine offsets s[0..128] (padded with
+// 0xFFFFFFFF, larger than any x used here).
+__device__ __forceinline__ uint32_t rank_below(const uint32_t *s, uint32_t x)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t step = 64; step > 0; step >>= 1) pos += s[pos + step - 1] < x ? step : 0u;
+    return pos + (s[pos] < x ? 1u : 0u);
+}
+
+}  // namespace
+
+// Static per-row word of the rank tables: rank | J << 8 | unreachable << 31.
+constexpr uint32_t kRankInvalid = 0x80000000u;
+
+template <int G, int LMAX, bool BOUNDS>
+__global__ void __launch_bounds__(kRankThreads)
+k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi, const uint64_t *__restrict__ offs,
+            uint64_t n_hits, int vec, const uint2 *__restrict__ tab, const uint32_t *__restrict__ rk_info,
+            const uint32_t *__restrict__ rk_sorted, uint32_t L, uint32_t rows, uint32_t nphi, uint32_t log2phi,
+            uint32_t shift, uint32_t n_tiles, uint32_t run_tiles, uint32_t runs_per_event,
+            uint16_t *__restrict__ acc)
+{
+    HOUGH_DYNAMIC_LDS(uint4, lds4);                  // 16-byte aligned: no static LDS in this kernel
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+    const uint32_t t = threadIdx.x, nt = blockDim.x;
+    const uint32_t lane = t & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6), nwaves = nt >> 6;
+    const uint32_t wmask = (1u << shift) - 1u;
+    const uint32_t ngrp = nphi >> 2;                 // 4-bucket groups per layer
+    const uint32_t item = blockIdx.x;
+    const uint32_t e = item / runs_per_event;
+    const uint32_t tile_lo = (item % runs_per_event) * run_tiles;
+    const uint32_t tile_hi = min(n_tiles, tile_lo + run_tiles);
+
+    // LDS: [bmin | bmax] (BOUNDS), the byte tables, the tile's sorted
+    // offsets, the list of (layer, bucket) entries that can be empty, its length
+    uint32_t *bmin = lds, *bmax = lds + (BOUNDS ? L * nphi : 0);
+    uint32_t *bytes = lds + (BOUNDS ? 2 * L * nphi : 0);         // [L][ngrp + 1] x {a word, span word}
+    uint32_t *srt = bytes + L * (ngrp + 1) * 2;                  // [L][kRankSortStride]
+    uint16_t *ivl = reinterpret_cast<uint16_t *>(srt + L * kRankSortStride);   // [L * nphi]
+    uint32_t &n_ivl = *(srt + L * kRankSortStride + (L * nphi + 1) / 2);       // the list's length
+
+    if (BOUNDS) {
+        for (uint32_t i = t; i < L * nphi; i += nt) {
+            bmin[i] = 0xFFFFFFFFu;
+            bmax[i] = 0u;
+        }
+        __syncthreads();
+        const uint64_t b = min(offs[e], n_hits);
+        uint64_t end = min(offs[e + 1], n_hits);
+        if (end < b) end = b;
+        rank_event_hits(layer, phi, b, end, t, nt, vec != 0, [&](uint32_t l, uint32_t ph) {
+            if (l < L) {
+                const uint32_t i = l * nphi + (ph >> shift), f = ph & wmask;
+                atomicMin(&bmin[i], f);
+                atomicMax(&bmax[i], f);
+            }
+        });
+    }
+
+    // The interval [lo, hi] of a (layer, bucket) entry i: the fine offsets at
+    // which its bin is empty; lo > hi when it never is.
+    auto interval = [&](uint32_t i, uint32_t &lo, uint32_t &hi) {
+        const uint32_t l = i >> log2phi, j = i & (nphi - 1);
+        if (BOUNDS) {
+            const uint32_t jn = l * nphi + ((j + 1) & (nphi - 1));
+            const bool ne = bmin[i] <= bmax[i], ne1 = bmin[jn] <= bmax[jn];
+            lo = ne ? bmax[i] + 1u : 0u;                     // may be W: never empty
+            hi = ne1 ? bmin[jn] : wmask;
+        } else {
+            const uint2 v = tab[(size_t(e) * L + l) * nphi + j];
+            lo = v.x;                                        // 0xFFFFFFFF: never empty
+            hi = v.x == 0xFFFFFFFFu ? 0u : v.x + v.y;
+        }
+    };
+    // Once per item: the entries with an interval (about a fifth of the
+    // buckets of a dense layer) go to a list, every byte-table entry starts
+    // at (a, span) = (0, 0), never empty, and only listed entries are
+    // ranked per tile.
+    if (t == 0) n_ivl = 0;
+    for (uint32_t i = t; i < L * (ngrp + 1) * 2; i += nt) bytes[i] = 0u;
+    __syncthreads();
+    for (uint32_t i0 = 0; i0 < L * nphi; i0 += nt) {
+        const uint32_t i = i0 + t;
+        bool has = false;
+        if (i < L * nphi) {
+            uint32_t lo, hi;
+            interval(i, lo, hi);
+            has = lo <= hi;
+        }
+        const uint64_t bal = __ballot(has);
+        uint32_t base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&n_ivl, uint32_t(__popcll(bal)));
+        base = __shfl(base, 0, 64);
+        if (has) ivl[base + __popcll(bal & ((1ull << lane) - 1ull))] = uint16_t(i);
+    }
+
+    uint16_t *eacc = acc + uint64_t(e) * rows * nphi;
+    for (uint32_t tile = tile_lo; tile < tile_hi; ++tile) {
+        // previous tile's rows are done with the byte tables; the list is complete
+        __syncthreads();
+        const uint32_t *gs = rk_sorted + size_t(tile) * L * kRankSortStride;
+        for (uint32_t i = t; i < L * kRankSortStride; i += nt) srt[i] = gs[i];
+        __syncthreads();
+        // (a, span) bytes of the listed entries for this tile
+        const uint32_t nl_ivl = n_ivl;
+        for (uint32_t q = t; q < nl_ivl; q += nt) {
+            const uint32_t i = ivl[q];
+            const uint32_t l = i >> log2phi, j = i & (nphi - 1);
+            uint32_t lo, hi;
+            interval(i, lo, hi);
+            const uint32_t *sl = srt + l * kRankSortStride;
+            const uint32_t a = rank_below(sl, lo);
+            const uint32_t sp = rank_below(sl, hi + 1u) - a;
+            uint8_t *bl = reinterpret_cast<uint8_t *>(bytes + l * (ngrp + 1) * 2);
+            const uint32_t g = j >> 2, k = j & 3;
+            bl[g * 8 + k] = uint8_t(a);
+            bl[g * 8 + 4 + k] = uint8_t(sp);
+            if (g == 0) {                                   // wrap group: buckets n_phi .. n_phi + 3
+                bl[ngrp * 8 + k] = uint8_t(a);
+                bl[ngrp * 8 + 4 + k] = uint8_t(sp);
+            }
+        }
+        __syncthreads();
+
+        const uint32_t r0 = tile * kRankTileRows;
+        const uint32_t tr = min(kRankTileRows, rows - r0);
+        const uint32_t rpw = (tr + nwaves - 1) / nwaves;
+        const uint32_t rb = r0 + wave * rpw, re = min(r0 + tr, rb + rpw);
+        uint32_t jc[LMAX];
+        uint32_t ca[LMAX][G], cs[LMAX][G];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            jc[l] = 0xFFFFFFFFu;
+#pragma unroll
+            for (int g = 0; g < G; ++g) ca[l][g] = cs[l][g] = 0;
+        }
+        const uint32_t n1 = min(L, 8u), n2 = L - n1;
+        const uint32_t bm1 = ((1u << n1) - 1u) * 0x01010101u, bm2 = ((1u << n2) - 1u) * 0x01010101u;
+        for (uint32_t r = rb; r < re; ++r) {
+            // the row's words for every layer in one scalar load
+            const uint32_t *info = rk_info + size_t(r) * 16;
+            uint32_t wv[LMAX];
+#pragma unroll
+            for (int l = 0; l < LMAX; ++l) wv[l] = info[l];
+            uint32_t m1[G], m2[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) m1[g] = m2[g] = 0;
+#pragma unroll
+            for (int l = 0; l < LMAX; ++l) {
+                if (uint32_t(l) < L) {
+                    const uint32_t w = wv[l];
+                    if (w & kRankInvalid) {
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            if (l < 8) m1[g] = (m1[g] >> 1) & 0x7F7F7F7Fu;
+                            else m2[g] = (m2[g] >> 1) & 0x7F7F7F7Fu;
+                        }
+                    } else {
+                        const uint32_t J = (w >> 8) & 0xFFFFu;
+                        const uint32_t R = (0x80u + (w & 0xFFu)) * 0x01010101u;
+                        if (J != jc[l]) {
+                            jc[l] = J;
+                            const uint2 *bg = reinterpret_cast<const uint2 *>(bytes + l * (ngrp + 1) * 2);
+                            const uint32_t sh = J & 3u;
+#pragma unroll
+                            for (int g = 0; g < G; ++g) {
+                                const uint32_t kk = ((J >> 2) + 64u * g + lane) & (ngrp - 1);
+                                const uint2 q0 = bg[kk], q1 = bg[kk + 1];
+                                ca[l][g] = __builtin_amdgcn_alignbyte(q1.x, q0.x, sh);
+                                cs[l][g] = __builtin_amdgcn_alignbyte(q1.y, q0.y, sh);
+                            }
+                        }
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const uint32_t x = R - ca[l][g];
+                            const uint32_t y = x - cs[l][g];
+                            const uint32_t occ = ~x | y;           // bit 7 of each byte: occupied
+                            if (l < 8) m1[g] = (occ & 0x80808080u) | ((m1[g] >> 1) & 0x7F7F7F7Fu);
+                            else m2[g] = (occ & 0x80808080u) | ((m2[g] >> 1) & 0x7F7F7F7Fu);
+                        }
+                    }
+                }
+            }
+            uint16_t *dst = eacc + size_t(r) * nphi;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const uint32_t a1 = (m1[g] >> (8 - n1)) & bm1;
+                const uint32_t a2 = n2 ? (m2[g] >> (8 - n2)) & bm2 : 0u;
+                uint2 out;
+                out.x = __builtin_amdgcn_perm(a2, a1, 0x05010400u);
+                out.y = __builtin_amdgcn_perm(a2, a1, 0x07030602u);
+                *reinterpret_cast<uint2 *>(dst + 256u * g + 4u * lane) = out;
+            }
+        }
+    }
+}
+
+namespace {
+
+template <int G, int LMAX>
+void launch_rank_g(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint32_t n_tiles, uint32_t run,
+                   uint32_t runs, uint32_t n_items, size_t lds, uint16_t *acc, hipStream_t s)
+{
+    const hough_grid_spec &g = c->spec;
+    if (bounds)
+        hipLaunchKernelGGL((k_vote_rank<G, LMAX, true>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer, h->phi,
+                           h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
+                           g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
+    else
+        hipLaunchKernelGGL((k_vote_rank<G, LMAX, false>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer,
+                           h->phi, h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
+                           g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
+}
+
+template <int G>
+void launch_rank(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint32_t n_tiles, uint32_t run,
+                 uint32_t runs, uint32_t n_items, size_t lds, uint16_t *acc, hipStream_t s)
+{
+    if (c->spec.n_layers <= 10)
+        launch_rank_g<G, 10>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
+    else
+        launch_rank_g<G, 16>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
+}
+
+size_t rank_lds_bytes(const hough_ctx *c, bool bounds)
+{
+    const size_t L = c->spec.n_layers, nphi = c->spec.n_phi;
+    return (bounds ? 2 * L * nphi * 4 : 0) + L * (nphi / 4 + 1) * 8 + L * kRankSortStride * 4 +
+           ((L * nphi + 1) / 2) * 4 + 4;
+}
+
+}  // namespace
+
+bool rank_vote_form(const hough_grid_spec &g)
+{
+    return (g.n_phi == 256 || g.n_phi == 512 || g.n_phi == 1024) && g.n_layers <= 16;
+}
+
+void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, const uint32_t *O, const uint8_t *V,
+                       std::vector<uint32_t> &info, std::vector<uint32_t> &sorted)
+{
+    const uint32_t L = g.n_layers;
+    const uint32_t wmask = (1u << shift) - 1u;
+    const uint32_t n_tiles = (rows + kRankTileRows - 1) / kRankTileRows;
+    info.assign(size_t(rows) * 16, 0u);
+    sorted.assign(size_t(n_tiles) * L * kRankSortStride, 0xFFFFFFFFu);
+    std::vector<uint32_t> f;
+    for (uint32_t t = 0; t < n_tiles; ++t) {
+        const uint32_t r0 = t * kRankTileRows, r1 = std::min(rows, r0 + kRankTileRows);
+        for (uint32_t l = 0; l < L; ++l) {
+            f.clear();
+            for (uint32_t r = r0; r < r1; ++r) f.push_back(O[size_t(l) * rows + r] & wmask);
+            std::sort(f.begin(), f.end());
+            std::copy(f.begin(), f.end(), sorted.begin() + (size_t(t) * L + l) * kRankSortStride);
+            for (uint32_t r = r0; r < r1; ++r) {
+                const uint32_t o = O[size_t(l) * rows + r];
+                const uint32_t rank = uint32_t(std::lower_bound(f.begin(), f.end(), o & wmask) - f.begin());
+                const uint32_t J = o >> shift;
+                info[size_t(r) * 16 + l] = rank | (J << 8) | (V[size_t(l) * rows + r] ? 0u : kRankInvalid);
+            }
+        }
+    }
+}
+
+bool rank_vote_usable(const hough_ctx *c, const uint16_t *acc)
+{
+    return c->d_rk_info != nullptr && (reinterpret_cast<uintptr_t>(acc) & 7) == 0 &&
+           rank_lds_bytes(c, false) <= c->max_lds_rank;
+}
+
+hipError_t launch_vote_rank(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s)
+{
+    const uint32_t E = h->n_events;
+    const uint32_t n_tiles = (c->rows + kRankTileRows - 1) / kRankTileRows;
+    const int vec = (reinterpret_cast<uintptr_t>(h->layer) & 3) == 0 && (reinterpret_cast<uintptr_t>(h->phi) & 15) == 0;
+    const uint64_t want = uint64_t(c->n_cu) * 2;
+    // whole events per item (bounds found in the kernel) when there are
+    // enough events to fill the device and the bounds fit in LDS; else one
+    // tile per item with the bounds from k_vote_bounds' table
+    const bool fits = rank_lds_bytes(c, true) <= c->max_lds_rank;
+    const bool bounds = c->tun.vote_items == 1 ? fits : c->tun.vote_items == 2 ? false : uint64_t(E) >= want && fits;
+    hipError_t err;
+    KernelTimer t;
+    if (!bounds && (err = launch_vote_bounds(c, h, s)) != hipSuccess) return err;
+    const uint32_t run = bounds ? n_tiles : 1;
+    const uint32_t runs = (n_tiles + run - 1) / run;
+    const uint32_t n_items = runs * E;
+    const size_t lds = rank_lds_bytes(c, bounds);
+    prof_begin(c, bounds ? "vote_rank_event" : "vote_rank_tile", s, &t);
+    switch (c->spec.n_phi) {
+    case 256: launch_rank<1>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s); break;
+    case 512: launch_rank<2>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s); break;
+    default: launch_rank<4>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s); break;
+    }
+    prof_end(c, s, &t);
+    return hipGetLastError();
+}
+
+}  // namespace hough

@@ -28,8 +28,9 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 
 
 def vote_space():
-    c = [dict(vote_algo=4, vote_rows=r, vote_threads=t, vote_wgs_per_cu=w)
-         for r in (8, 16) for t in (128, 256) for w in (2, 4, 8, 16)]
+    c = [dict(vote_algo=5, vote_items=i) for i in (1, 2)]
+    c += [dict(vote_algo=4, vote_rows=r, vote_threads=t, vote_wgs_per_cu=w)
+          for r in (8, 16) for t in (128, 256) for w in (2, 4, 8, 16)]
     c += [dict(vote_algo=3, vote_threads=t) for t in (256, 512)]
     c += [dict(vote_algo=1)]
     return c

@@ -205,7 +205,7 @@ def gap_layout_batch(n_phi):
     return synth.concat_events(evs)
 
 
-@pytest.mark.parametrize("kw", [dict(n_phi=64, n_qpt=16), dict(n_phi=1024, n_qpt=8),
+@pytest.mark.parametrize("kw", [dict(n_phi=64, n_qpt=16), dict(n_phi=1024, n_qpt=8), dict(n_phi=512, n_qpt=200),
                                 dict(n_phi=64, n_qpt=8, n_d0=8, d0_lo_mm=-120.0, d0_hi_mm=120.0, n_z0=0)])
 def test_vote_forms_on_layer_layouts(H, kw):
     spec = small_spec(**kw)
@@ -214,16 +214,37 @@ def test_vote_forms_on_layer_layouts(H, kw):
     res = run_gpu(H, spec, batch, rz=False)
     per_hit = H.acc_numpy(run_gpu(H, spec, batch, tuning=dict(vote_algo=1), rz=False)["acc"])
     gaps = H.acc_numpy(run_gpu(H, spec, batch, tuning=dict(vote_algo=3), rz=False)["acc"])
+    direct = H.acc_numpy(run_gpu(H, spec, batch, tuning=dict(vote_algo=4), rz=False)["acc"])
     np.testing.assert_array_equal(H.acc_numpy(res["acc"]), per_hit)
     np.testing.assert_array_equal(gaps, per_hit)
+    np.testing.assert_array_equal(direct, per_hit)
     for e in range(batch.n_events):
         check_event(H, tab, res, batch, e)
 
 
+RANK_SPECS = [dict(n_phi=256, n_qpt=16), dict(n_phi=512, n_qpt=300), dict(n_phi=1024, n_qpt=129),
+              dict(n_phi=256, n_qpt=64, n_d0=8, d0_lo_mm=-120.0, d0_hi_mm=120.0, n_z0=0)]
+
+
+@pytest.mark.parametrize("kw", RANK_SPECS)
+@pytest.mark.parametrize("items", [0, 1, 2])
+def test_rank_vote_form(H, kw, items):
+    """The rank form of the vote (four cells per operation in tile rank
+    space), with whole events per workgroup (bounds in LDS) and one tile per
+    workgroup (bounds table), on ragged events, the adversarial layer
+    layouts and a displaced grid with unreachable rows."""
+    spec = small_spec(**kw)
+    tab = oracle.Tables(spec)
+    for batch in (ragged_batch(), gap_layout_batch(spec["n_phi"])):
+        res = run_gpu(H, spec, batch, tuning=dict(vote_algo=5, vote_items=items), rz=False)
+        for e in range(batch.n_events):
+            check_event(H, tab, res, batch, e)
+
+
 def test_unaligned_hit_arrays_and_accumulator(H):
     """Hit arrays that start one element past an aligned address and an
-    accumulator that is 4- but not 16-byte aligned take the scalar load and
-    store paths of the vote; results are unchanged."""
+    accumulator that is 4- but not 8-byte aligned take the scalar load paths
+    and the fallback vote form; results are unchanged."""
     import torch
     spec = small_spec(n_phi=256, n_qpt=16)
     batch = ragged_batch()
@@ -299,6 +320,8 @@ def test_peak_and_rz_capacity_overflow(H):
     # up to about 6000 members per cell: past every member list, so the slow path
     (dict(rz_counter_bits=16), dict(n_phi=2, n_qpt=4, n_cot=9)),
     (None, dict(z0_lo_um=-2147483000, z0_hi_um=2147483000, n_z0=64)),  # general kernel
+    (None, dict(cot_lo=1.2, cot_hi=-1.2)),          # Z decreasing in the cot bin
+    (None, dict(n_cot=100)),                        # a last pass of 36 cot bins
 ])
 def test_rz_kernel_variants(H, tuning, kw):
     spec = small_spec(**kw)

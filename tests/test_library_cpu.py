@@ -141,3 +141,17 @@ int main() {
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-I",
                            os.path.join(ROOT, "paper_1310_7556_amd", "csrc"), str(src), "-o", str(exe)])
     subprocess.check_call([str(exe)])
+
+
+@pytest.mark.parametrize("cot", [(-1.2, 1.2), (1.2, -1.2), (0.5, 0.5)])
+def test_z_shift_monotone_in_cot_bin(cot):
+    """The rz kernel leaves a member out of a pass of cot bins when its z
+    lies outside [min, max + span) of the pass's end values, which is exact
+    only if Z[k][l][j] is monotone in j; it is (linear cot centres, a
+    positive arc length, monotone rounding) for rising, falling and flat
+    cot ranges."""
+    spec = synth.grid_spec("c2_single_1ktrk_rz")
+    spec.update(cot_lo=cot[0], cot_hi=cot[1])
+    _, _, Z = hough.build_tables(spec)
+    d = np.diff(Z.astype(np.int64), axis=2)
+    assert (d >= 0).all() or (d <= 0).all()
