@@ -166,7 +166,8 @@ typedef struct {
     uint32_t vote_rows;             /* accumulator rows per LDS tile */
     uint32_t vote_threads;          /* threads per vote workgroup (multiple of 64, <= 1024) */
     uint32_t vote_wgs_per_cu;       /* persistent vote grid: workgroups per compute unit */
-    uint32_t peak_rows;             /* accumulator rows per peak-finding tile */
+    uint32_t peak_rows;             /* accumulator rows per peak-finding tile (per wavefront strip in
+                                       peak form 2) */
     uint32_t rz_waves_per_cu;       /* persistent rz grid: waves per compute unit */
     uint32_t vote_algo;             /* 0 = default (5 where usable, else 4), 1 = per-hit LDS atomics,
                                        2 = global atomics, 3 = hit-gap lists, 4 = bucket bounds (direct
@@ -178,6 +179,9 @@ typedef struct {
     uint32_t vote_items;            /* vote form 5: 0 = automatic, 1 = a whole event per workgroup (bucket
                                        bounds found in LDS), 2 = one row tile per workgroup (bounds from a
                                        table pass over the hits) */
+    uint32_t peak_algo;             /* peak search: 0 = default (2 where usable, else 1), 1 = tiles staged
+                                       in LDS, 2 = row window in registers (n_d0 == 1, n_phi 256, 512 or
+                                       1024, accumulator 16-byte aligned, 8 for n_phi 256) */
 } hough_tuning;
 
 /* ---- context --------------------------------------------------------- */

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libhough.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["api.hip", "k_util.hip", "k_bucket.hip", "k_vote.hip", "k_vote_gap.hip", "k_vote_direct.hip", "k_vote_rank.hip", "k_peaks.hip", "k_rz.hip",
+HIP_SOURCES = ["api.hip", "k_util.hip", "k_bucket.hip", "k_vote.hip", "k_vote_gap.hip", "k_vote_direct.hip", "k_vote_rank.hip", "k_peaks.hip", "k_peaks_rows.hip", "k_rz.hip",
                "k_cluster.hip", "k_fit.hip"]
 CXX_SOURCES = ["tables.cpp"]
 

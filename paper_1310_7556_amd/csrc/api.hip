@@ -14,8 +14,6 @@ using namespace hough;
 
 namespace {
 
-constexpr uint32_t kMaxRzWavesPerCu = 16;
-
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -88,6 +86,7 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.vote_algo == 4 && !hough::direct_vote_usable(c)) return false;
     if (t.vote_algo == 5 && !c->d_rk_info) return false;
     if (t.vote_items > 2) return false;
+    if (t.peak_algo > 2) return false;
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 4 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16)
         return false;
@@ -216,16 +215,22 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
         const int64_t span = int64_t(spec->z0_hi_um) - int64_t(spec->z0_lo_um);
         const BinMagic bm = make_binmagic_min(uint64_t(span), spec->n_z0);
         bool ok = bm.ok;
-        Zl.resize(Z.size());
-        for (size_t i = 0; ok && i < Z.size(); ++i) {
-            const int64_t zl = int64_t(Z[i]) + spec->z0_lo_um;
-            ok = zl >= INT32_MIN && zl <= int64_t(INT32_MAX) + 1 - span;
-            Zl[i] = int32_t(zl);
-        }
-        c->rz_fast = ok;
+        // stored [k][j][16 layers] so that a lane (one cot bin) reads all
+        // its layers' values as 64 contiguous bytes; layers past n_layers
+        // hold 0 (the fast kernel's padding members use layer 15)
+        Zl.assign(size_t(spec->n_qpt) * spec->n_cot * kMaxLayers, 0);
+        for (uint32_t k = 0; ok && k < spec->n_qpt; ++k)
+            for (uint32_t l = 0; ok && l < spec->n_layers; ++l)
+                for (uint32_t j = 0; ok && j < spec->n_cot; ++j) {
+                    const size_t i = (size_t(k) * spec->n_layers + l) * spec->n_cot + j;
+                    const int64_t zl = int64_t(Z[i]) + spec->z0_lo_um;
+                    ok = zl >= INT32_MIN && zl <= int64_t(INT32_MAX) + 1 - span;
+                    Zl[(size_t(k) * spec->n_cot + j) * kMaxLayers + l] = int32_t(zl);
+                }
+        c->rz_fast = ok && spec->n_layers < kMaxLayers;
         c->rz_magic_m = bm.m;
         c->rz_magic_s = bm.s;
-        if (!ok) Zl.clear();
+        if (!c->rz_fast) Zl.clear();
     }
 
     std::vector<uint32_t> rk_info, rk_sorted;
@@ -510,7 +515,15 @@ int hough_get_tables(const hough_ctx *ctx, uint32_t *O, uint8_t *V, size_t nOV, 
     if (O) e = hipMemcpy(O, ctx->d_O, need * 4, hipMemcpyDeviceToHost);
     if (e == hipSuccess && V) e = hipMemcpy(V, ctx->d_V, need, hipMemcpyDeviceToHost);
     if (e == hipSuccess && Z) e = hipMemcpy(Z, ctx->d_Z, needz * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && Zl) e = hipMemcpy(Zl, ctx->d_Zl, needz * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && Zl) {
+        // the device copy is [k][j][16 layers]; return it as [k][l][j]
+        std::vector<int32_t> t(size_t(g.n_qpt) * g.n_cot * kMaxLayers);
+        e = hipMemcpy(t.data(), ctx->d_Zl, t.size() * 4, hipMemcpyDeviceToHost);
+        for (uint32_t k = 0; e == hipSuccess && k < g.n_qpt; ++k)
+            for (uint32_t l = 0; l < g.n_layers; ++l)
+                for (uint32_t j = 0; j < g.n_cot; ++j)
+                    Zl[(size_t(k) * g.n_layers + l) * g.n_cot + j] = t[(size_t(k) * g.n_cot + j) * kMaxLayers + l];
+    }
     return e == hipSuccess ? HOUGH_OK : HOUGH_EDEVICE;
 }
 

@@ -64,7 +64,7 @@ struct hough_ctx {
     uint32_t *d_O = nullptr;     // [L][rows] + kOPad zero entries
     uint8_t *d_V = nullptr;      // [L][rows]
     int32_t *d_Z = nullptr;      // [n_qpt][L][n_cot]
-    int32_t *d_Zl = nullptr;     // [n_qpt][L][n_cot] = Z + z0_lo, when rz_fast
+    int32_t *d_Zl = nullptr;     // [n_qpt][n_cot][16] = Z + z0_lo (0 past n_layers), when rz_fast
     bool all_valid = true;       // every (layer, row) reachable
     // rz fast path: z - (Z + z0_lo) is exact in uint32 arithmetic and the z0
     // bin is one multiply-high (see fastdiv.h BinMagic)
@@ -91,7 +91,7 @@ struct hough_ctx {
     uint64_t *d_scan_off = nullptr;    // [scan_blocks_max + 1] their exclusive prefix
     uint64_t scan_blocks_max = 0;
     uint2 *d_dir_tab = nullptr;        // [max_events][L][n_phi] direct vote: per-bucket {lo, span}
-    uint32_t *d_rk_info = nullptr;     // [rows][16] rank vote: rank | J << 8 | unreachable << 31
+    uint32_t *d_rk_info = nullptr;     // [rows][32] rank vote: J | unreachable << 31, then (0x80 + rank) x 0x01010101
     uint32_t *d_rk_sorted = nullptr;   // [tiles][L][kRankSortStride] rank vote: sorted fine offsets
     size_t max_lds_direct = 65536;     // LDS budget of the direct vote's table staging
     size_t max_lds_rank = 65536;       // LDS budget of the rank vote (two workgroups per compute unit)
@@ -135,6 +135,15 @@ struct PeakScratch {
     uint64_t scan_blocks_max;
 };
 PeakScratch ctx_peak_scratch(hough_ctx *c);
+// Row-window peak form (k_peaks_rows.hip): cells per lane (4, 8 or 16)
+// when it applies to this context and accumulator, else 0; rows per
+// wavefront strip; one pass (count or write) over n_events accumulators
+// with the tile counts and offsets of ps.
+constexpr uint32_t kPeakThreads = 256;
+uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc);
+uint32_t peak_rows_strip(const hough_ctx *c);
+hipError_t launch_peaks_rows_pass(hough_ctx *c, bool write, const uint16_t *acc, uint32_t n_events,
+                                  hough_peak *peaks, uint64_t capacity, const PeakScratch &ps, hipStream_t s);
 // Number of tiles the peak search of n_events accumulators at `acc` uses.
 uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc);
 // timed = false: no per-kernel timing (no HIP events are created)
@@ -172,6 +181,10 @@ hipError_t launch_vote_rank(hough_ctx *c, const hough_hits *h, uint16_t *acc, hi
 uint32_t gap_rows(const hough_ctx *c);
 bool gap_vote_usable(const hough_ctx *c);
 uint32_t rz_blocks(const hough_ctx *c);
+// Persistent rz workgroups at most (each owns an n_z0 histogram of the
+// context's slow-path scratch).
+constexpr uint32_t kMaxRzWavesPerCu = 16;
+inline uint32_t rz_blocks_max(const hough_ctx *c) { return uint32_t(c->n_cu) * kMaxRzWavesPerCu; }
 uint64_t max_peak_tiles(const hough_ctx *c);
 
 // Exclusive prefix of n uint32 counts into n + 1 uint64 offsets (one

@@ -466,7 +466,6 @@ k_peaks_count(const uint32_t *__restrict__ cnt, uint32_t n_d0, uint32_t n_qpt, u
 
 namespace {
 
-constexpr uint32_t kPeakThreads = 256;
 
 // LDS of one peak tile of rp rows: popcounts of the staged rows (bytes in
 // the scalar kernel, uint16 in the vector one, which with WRITE adds the raw
@@ -494,6 +493,10 @@ uint32_t fit_rows(const hough_ctx *c, bool vec)
 
 uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc)
 {
+    if (peak_rows_cells_per_lane(c, acc)) {
+        const uint32_t R = peak_rows_strip(c);
+        return uint64_t(n_events) * ((c->spec.n_qpt + R - 1) / R);
+    }
     const bool vec = c->spec.n_phi >= 8 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0 &&
                      fit_rows(c, true) > 0;
     const uint32_t rp = fit_rows(c, vec);
@@ -512,6 +515,27 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
                         bool timed)
 {
     hipError_t err;
+    KernelTimer t;
+    t.name = nullptr;
+    if (peak_rows_cells_per_lane(c, acc)) {
+        const uint32_t R = peak_rows_strip(c);
+        const uint32_t n_strips = (c->spec.n_qpt + R - 1) / R;
+        if (n_events == 0)
+            return launch_scan_counts(c, ps.tile_counts, 0, ps.tile_off, 1, event_peak_offsets, s, ps.scan_part,
+                                      ps.scan_off, ps.scan_blocks_max, timed);
+        if (timed) prof_begin(c, "peaks_count", s, &t);
+        err = launch_peaks_rows_pass(c, false, acc, n_events, peaks, capacity, ps, s);
+        if (timed) prof_end(c, s, &t);
+        if (err != hipSuccess) return err;
+        if ((err = launch_scan_counts(c, ps.tile_counts, uint64_t(n_events) * n_strips, ps.tile_off, n_strips,
+                                      event_peak_offsets, s, ps.scan_part, ps.scan_off, ps.scan_blocks_max,
+                                      timed)) != hipSuccess)
+            return err;
+        if (timed) prof_begin(c, "peaks_write", s, &t);
+        err = launch_peaks_rows_pass(c, true, acc, n_events, peaks, capacity, ps, s);
+        if (timed) prof_end(c, s, &t);
+        return err;
+    }
     const bool vec = c->spec.n_phi >= 8 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0 &&
                      fit_rows(c, true) > 0;
     const uint32_t rp = fit_rows(c, vec);
@@ -523,8 +547,6 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
                                   ps.scan_off, ps.scan_blocks_max, timed);
     }
     const size_t lds = peaks_lds_bytes(c, rp, vec);
-    KernelTimer t;
-    t.name = nullptr;
     if (timed) prof_begin(c, "peaks_count", s, &t);
     if (vec)
         hipLaunchKernelGGL(k_peaks_vec<false>, dim3(uint32_t(n_items)), dim3(kPeakThreads),

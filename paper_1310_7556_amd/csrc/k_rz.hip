@@ -46,7 +46,7 @@ struct RzParams {
     const uint32_t *O;            // [L][rows]
     const uint8_t *V;
     const int32_t *Z;             // [K][L][C]
-    const int32_t *Zl;            // [K][L][C] = Z + z0_lo (fast path)
+    const int32_t *Zl;            // [K][C][16] = Z + z0_lo, 0 past n_layers (fast path)
     const uint2 *peaks;
     uint64_t peak_capacity;
     const uint64_t *poff;         // [E + 1]
@@ -64,12 +64,16 @@ struct RzParams {
     FastDiv32 fd;
     int lds_ok;                   // general kernel: the uint16 histogram fits in LDS
     uint32_t bm, bs;              // fast path: bin = mulhi(u, bm) >> bs
+    uint32_t span24;              // MUL == 2: span (< 2^24, with bm < 2^24 and bs == 0)
     uint32_t hw;                  // fast path: counter dwords per lane
     uint32_t mcap;                // fast path: member list capacity
 };
 
 // candidates taken per work-counter ticket by the fast kernel
 constexpr uint32_t kRzChunk = 8;
+
+// count field of a record that k_rz_vote_fast leaves to k_rz_redo
+constexpr uint32_t kRzRedo = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -320,8 +324,14 @@ __host__ __device__ inline uint32_t rz_fast_lds_dwords(uint32_t hw, uint32_t mca
     return hw * 64 + 96 + 32 + 2 * rz_list_dwords(mcap);
 }
 
-// SHIFT: the bin multiply needs its extra right shift (bs > 0).
-template <int BITS, bool SHIFT>
+// MUL: how the bin is found from u = z - (Z + z0_lo): 0 = min(mulhi(u, bm),
+// n_z0); 1 = the same with the extra right shift bs; 2 = mulhi24(min(u,
+// span), bm), two full-rate operations where the 32-bit multiply-high is
+// quarter rate: when span and bm are below 2^24 (and bs == 0) the 24-bit
+// multiply-high is exact, min(u, span) keeps every in-range u and maps the
+// others to span, and floor(span * bm / 2^32) is exactly n_z0 (bm =
+// ceil(n_z0 2^32 / span) and span < 2^32), the trash bin.
+template <int BITS, int MUL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))   // <= 128 VGPRs
 k_rz_vote_fast(RzParams P)
 {
@@ -348,7 +358,6 @@ k_rz_vote_fast(RzParams P)
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
     for (uint32_t i = lane; i < P.hw * 64; i += 64) hist[i] = 0;
     __syncthreads();
-    uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
     for (;;) {
         // a chunk of consecutive candidates per ticket (one contended atomic
         // per kRzChunk candidates); the fetch itself as in k_rz_vote
@@ -364,23 +373,29 @@ k_rz_vote_fast(RzParams P)
         const RzCand r = rz_decode_rec(P, c, rec);
         const uint32_t k = r.k, p = r.p;
         // all layers' (Z + z0_lo) for this lane's first cot bin, issued now
-        // so that they arrive with the member search's loads
-        // Layers >= n_layers are never read except the padding layer 15,
-        // whose value must be 0; the others load a valid row (clamped
-        // index), so every load is unconditional and branch-free.
-        const int32_t *zrow = P.Zl + size_t(k) * nl * P.n_cot;
+        // so that they arrive with the member search's loads: the table is
+        // [k][cot][16 layers], so they are 64 contiguous bytes (4 loads; a
+        // lane past the last cot bin reads the last one).  Layers >=
+        // n_layers hold 0, which the padding layer 15 needs.
+        const int32_t *zrow = P.Zl + size_t(k) * P.n_cot * kMaxLayers;
         uint32_t zr[kMaxLayers], zn[kMaxLayers];
-        {
-            const int32_t *zl0 = zrow + min(lane, P.n_cot - 1);
+        auto load_rows = [&](uint32_t jj, uint32_t (&zz)[kMaxLayers]) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(zrow + size_t(min(jj, P.n_cot - 1)) * kMaxLayers);
 #pragma unroll
-            for (uint32_t l = 0; l + 1 < kMaxLayers; ++l) zr[l] = uint32_t(zl0[size_t(min(l, nl - 1)) * P.n_cot]);
-            zr[kMaxLayers - 1] = 0u;
-        }
-        // the first pass's boundary values: lanes 0..15 read Zl at its first
-        // cot bin, lanes 16..31 at its last, one layer each (clamped index)
+            for (uint32_t g = 0; g < kMaxLayers / 4; ++g) {
+                const uint4 v = q[g];
+                zz[4 * g] = v.x;
+                zz[4 * g + 1] = v.y;
+                zz[4 * g + 2] = v.z;
+                zz[4 * g + 3] = v.w;
+            }
+        };
+        load_rows(lane, zr);
+        // the first pass's boundary values: lanes 0..15 read layer `lane` at
+        // its first cot bin, lanes 16..31 layer `lane - 16` at its last
         auto boundary = [&](uint32_t jp) {
-            const uint32_t jb = lane < 16 ? jp : min(jp + 63u, P.n_cot - 1);
-            return zrow[size_t(min(lane & 15u, nl - 1)) * P.n_cot + min(jb, P.n_cot - 1)];
+            const uint32_t jb = lane < 16 ? jp : jp + 63u;
+            return zrow[size_t(min(jb, P.n_cot - 1)) * kMaxLayers + (lane & 15u)];
         };
         int32_t tbv = boundary(0);
 
@@ -503,10 +518,7 @@ k_rz_vote_fast(RzParams P)
                 __syncthreads();
                 // next pass's rows (after the last pass they are loaded and
                 // not used: the index is clamped, so the loads stay in bounds)
-                const int32_t *zln = zrow + min(j + 64, P.n_cot - 1);
-#pragma unroll
-                for (uint32_t l = 0; l + 1 < kMaxLayers; ++l) zn[l] = uint32_t(zln[size_t(min(l, nl - 1)) * P.n_cot]);
-                zn[kMaxLayers - 1] = 0u;
+                load_rows(j + 64, zn);
                 // all members in one flat loop, eight per step (a last step of
                 // four): 16-byte LDS reads give four z each, 4-byte reads
                 // their layers (so (Z + z0_lo) is a register-indexed move).  Per member: the
@@ -541,9 +553,14 @@ k_rz_vote_fast(RzParams P)
                     for (int q = 0; q < Q; ++q) {
                         const uint32_t lq = (lw[q >> 2] >> (8 * (q & 3))) & 0xFFu;
                         const uint32_t u = zm[q] - zr[lq];
-                        uint32_t t = __umulhi(u, P.bm);
-                        if (SHIFT) t >>= P.bs;
-                        b[q] = min(t, P.n_z0);
+                        if (MUL == 2) {
+                            // both factors below 2^24: the 24-bit multiply-high
+                            b[q] = uint32_t((uint64_t(min(u, P.span24) & 0xFFFFFFu) * (P.bm & 0xFFFFFFu)) >> 32);
+                        } else {
+                            uint32_t t = __umulhi(u, P.bm);
+                            if (MUL == 1) t >>= P.bs;
+                            b[q] = min(t, P.n_z0);
+                        }
                         sh[q] = b[q] << BSH;   // field offset, taken mod 32
                     }
 #pragma unroll
@@ -585,16 +602,43 @@ k_rz_vote_fast(RzParams P)
             }
         }
         // an overflowed count makes every result of this candidate suspect
-        // (a carry reaches the next bin): redo it exactly
+        // (a carry reaches the next bin), and a candidate with more members
+        // than the list holds was not counted: its record is marked and
+        // k_rz_redo recomputes it exactly
         if (nm > lim || (BITS <= 8 && __ballot(ovf) != 0)) {
-            best_c = 0;
-            best_j = lane;
-            best_b = 0;
-            rz_slow(P, r.eb, r.bo, k, p, r.mask, g, lane, best_c, best_j, best_b);
-            if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
+            P.out4[2 * c] = make_uint2(r.pk, 0u);
+            P.out4[2 * c + 1] = make_uint2(kRzRedo, nm);
+        } else {
+            rz_finish(P, c, r.pk, nm, best_c, best_j, best_b);
         }
-        rz_finish(P, c, r.pk, nm, best_c, best_j, best_b);
       }
+    }
+}
+
+// The exact slow path for the records k_rz_vote_fast marked (count ==
+// kRzRedo): one wave per 64 records, each marked candidate recomputed with
+// the global-memory histogram of the wave's workgroup (grid-stride over
+// record groups; at most rz_blocks workgroups, one histogram each).
+__global__ void __launch_bounds__(64) k_rz_redo(RzParams P)
+{
+    const uint32_t lane = threadIdx.x;
+    const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
+    uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
+    for (uint64_t c0 = uint64_t(blockIdx.x) * 64; c0 < total; c0 += uint64_t(gridDim.x) * 64) {
+        const uint64_t c = c0 + lane;
+        const bool redo = c < total && P.out4[2 * c + 1].x == kRzRedo;
+        uint64_t bal = __ballot(redo);
+        while (bal) {
+            const uint32_t b = __ffsll(static_cast<unsigned long long>(bal)) - 1;
+            bal &= bal - 1;
+            const uint64_t cc = c0 + b;
+            const RzCand r = rz_decode(P, cc);
+            const uint32_t nm = uni(P.out4[2 * cc + 1].y);     // the fast kernel's member count
+            uint32_t best_c = 0, best_j = 0, best_b = 0;
+            rz_slow(P, r.eb, r.bo, r.k, r.p, r.mask, g, lane, best_c, best_j, best_b);
+            if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
+            rz_finish(P, cc, r.pk, nm, best_c, best_j, best_b);
+        }
     }
 }
 
@@ -669,6 +713,29 @@ uint32_t rz_blocks(const hough_ctx *c)
     const uint32_t w = c->tun.rz_waves_per_cu ? c->tun.rz_waves_per_cu : 8;
     return uint32_t(c->n_cu) * w;
 }
+
+namespace {
+
+template <int BITS>
+void launch_fast(int mul, uint32_t blocks, size_t lds, hipStream_t s, const RzParams &P)
+{
+    if (mul == 2)
+        hipLaunchKernelGGL((k_rz_vote_fast<BITS, 2>), dim3(blocks), dim3(64), lds, s, P);
+    else if (mul == 1)
+        hipLaunchKernelGGL((k_rz_vote_fast<BITS, 1>), dim3(blocks), dim3(64), lds, s, P);
+    else
+        hipLaunchKernelGGL((k_rz_vote_fast<BITS, 0>), dim3(blocks), dim3(64), lds, s, P);
+}
+
+// An upper bound of the rz records of a call (the kernels read the true
+// count on the device): the capacity, and no more than the candidates.
+uint64_t rz_records_bound(const hough_ctx *c, const hough_hits *h, uint64_t peak_capacity, uint64_t capacity)
+{
+    const uint32_t cap = c->spec.rz_max_candidates;
+    return std::min<uint64_t>(capacity, cap ? uint64_t(h->n_events) * cap : peak_capacity);
+}
+
+}  // namespace
 
 hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks, uint64_t peak_capacity,
                      const uint64_t *poff, hough_rz *out, uint64_t capacity, uint64_t *roff, hipStream_t s)
@@ -758,19 +825,21 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         P.mcap = mcap;
         P.lds_ok = 0;
         prof_begin(c, "rz_vote", s, &t);
-        const bool shift = P.bs != 0;
-        if (bits == 4 && shift)
-            hipLaunchKernelGGL((k_rz_vote_fast<4, true>), dim3(blocks), dim3(64), fast_lds, s, P);
-        else if (bits == 4)
-            hipLaunchKernelGGL((k_rz_vote_fast<4, false>), dim3(blocks), dim3(64), fast_lds, s, P);
-        else if (bits == 8 && shift)
-            hipLaunchKernelGGL((k_rz_vote_fast<8, true>), dim3(blocks), dim3(64), fast_lds, s, P);
+        const int mul = P.bs != 0 ? 1 : (P.span < (1u << 24) && P.bm < (1u << 24)) ? 2 : 0;
+        P.span24 = uint32_t(P.span);
+        if (bits == 4)
+            launch_fast<4>(mul, blocks, fast_lds, s, P);
         else if (bits == 8)
-            hipLaunchKernelGGL((k_rz_vote_fast<8, false>), dim3(blocks), dim3(64), fast_lds, s, P);
-        else if (shift)
-            hipLaunchKernelGGL((k_rz_vote_fast<16, true>), dim3(blocks), dim3(64), fast_lds, s, P);
+            launch_fast<8>(mul, blocks, fast_lds, s, P);
         else
-            hipLaunchKernelGGL((k_rz_vote_fast<16, false>), dim3(blocks), dim3(64), fast_lds, s, P);
+            launch_fast<16>(mul, blocks, fast_lds, s, P);
+        prof_end(c, s, &t);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        // candidates the fast kernel marked; the grid covers every record
+        // group and uses at most the slow path's histograms
+        const uint64_t groups = std::max<uint64_t>(1, (rz_records_bound(c, h, peak_capacity, capacity) + 63) / 64);
+        prof_begin(c, "rz_redo", s, &t);
+        hipLaunchKernelGGL(k_rz_redo, dim3(uint32_t(std::min<uint64_t>(groups, rz_blocks_max(c)))), dim3(64), 0, s, P);
         prof_end(c, s, &t);
         return hipGetLastError();
     }

@@ -49,13 +49,25 @@ __device__ __forceinline__ void rank_event_hits(const uint8_t *__restrict__ laye
         const uint64_t nq = (end - a) >> 2;
         const uint32_t *l4 = reinterpret_cast<const uint32_t *>(layer + a);
         const uint4 *p4 = reinterpret_cast<const uint4 *>(phi + a);
-        for (uint64_t q = t; q < nq; q += nt) {
-            const uint32_t lw = l4[q];
-            const uint4 pw = p4[q];
-            f(lw & 0xFFu, pw.x);
-            f((lw >> 8) & 0xFFu, pw.y);
-            f((lw >> 16) & 0xFFu, pw.z);
-            f(lw >> 24, pw.w);
+        // four groups of four hits per thread per step, all loads issued
+        // before any is used, so a step waits for memory once
+        constexpr uint32_t U = 4;
+        for (uint64_t q0 = t; q0 < nq; q0 += U * uint64_t(nt)) {
+            uint32_t lw[U];
+            uint4 pw[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint64_t q = q0 + u * uint64_t(nt);
+                lw[u] = q < nq ? l4[q] : 0xFFFFFFFFu;       // layer 255: ignored
+                pw[u] = q < nq ? p4[q] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                f(lw[u] & 0xFFu, pw[u].x);
+                f((lw[u] >> 8) & 0xFFu, pw[u].y);
+                f((lw[u] >> 16) & 0xFFu, pw[u].z);
+                f(lw[u] >> 24, pw[u].w);
+            }
         }
         tail = a + (nq << 2);
     }
@@ -74,10 +86,13 @@ __device__ __forceinline__ uint32_t rank_below(const uint32_t *s, uint32_t x)
 
 }  // namespace
 
-// Static per-row word of the rank tables: rank | J << 8 | unreachable << 31.
+// Static per-row words of the rank tables: [0, 16) J | unreachable << 31 per
+// layer, [16, 32) (0x80 + rank) in every byte per layer.
 constexpr uint32_t kRankInvalid = 0x80000000u;
 
-template <int G, int LMAX, bool BOUNDS>
+// NL > 0: exactly NL layers; NL == 0: L (at most 16) at run time.  ALLV:
+// every (row, layer) pair is reachable.
+template <int G, int NL, bool ALLV, bool BOUNDS>
 __global__ void __launch_bounds__(kRankThreads)
 k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi, const uint64_t *__restrict__ offs,
             uint64_t n_hits, int vec, const uint2 *__restrict__ tab, const uint32_t *__restrict__ rk_info,
@@ -85,6 +100,7 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             uint32_t shift, uint32_t n_tiles, uint32_t run_tiles, uint32_t runs_per_event,
             uint16_t *__restrict__ acc)
 {
+    constexpr int LMAX = NL > 0 ? NL : 16;
     HOUGH_DYNAMIC_LDS(uint4, lds4);                  // 16-byte aligned: no static LDS in this kernel
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     const uint32_t t = threadIdx.x, nt = blockDim.x;
@@ -145,19 +161,28 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
     if (t == 0) n_ivl = 0;
     for (uint32_t i = t; i < L * (ngrp + 1) * 2; i += nt) bytes[i] = 0u;
     __syncthreads();
-    for (uint32_t i0 = 0; i0 < L * nphi; i0 += nt) {
-        const uint32_t i = i0 + t;
-        bool has = false;
-        if (i < L * nphi) {
-            uint32_t lo, hi;
-            interval(i, lo, hi);
-            has = lo <= hi;
+    // eight entries per thread per step, their bounds read before any is
+    // used (one memory wait per step when they come from the table)
+    constexpr uint32_t UI = 8;
+    for (uint32_t i0 = 0; i0 < L * nphi; i0 += UI * nt) {
+        bool has[UI];
+#pragma unroll
+        for (uint32_t u = 0; u < UI; ++u) {
+            const uint32_t i = i0 + u * nt + t;
+            uint32_t lo = 1, hi = 0;
+            if (i < L * nphi) interval(i, lo, hi);
+            has[u] = lo <= hi;
         }
-        const uint64_t bal = __ballot(has);
-        uint32_t base = 0;
-        if (lane == 0 && bal) base = atomicAdd(&n_ivl, uint32_t(__popcll(bal)));
-        base = __shfl(base, 0, 64);
-        if (has) ivl[base + __popcll(bal & ((1ull << lane) - 1ull))] = uint16_t(i);
+#pragma unroll
+        for (uint32_t u = 0; u < UI; ++u) {
+            if (i0 + u * nt >= L * nphi) break;
+            const uint32_t i = i0 + u * nt + t;
+            const uint64_t bal = __ballot(has[u]);
+            uint32_t base = 0;
+            if (lane == 0 && bal) base = atomicAdd(&n_ivl, uint32_t(__popcll(bal)));
+            base = __shfl(base, 0, 64);
+            if (has[u]) ivl[base + __popcll(bal & ((1ull << lane) - 1ull))] = uint16_t(i);
+        }
     }
 
     uint16_t *eacc = acc + uint64_t(e) * rows * nphi;
@@ -200,30 +225,42 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
 #pragma unroll
             for (int g = 0; g < G; ++g) ca[l][g] = cs[l][g] = 0;
         }
-        const uint32_t n1 = min(L, 8u), n2 = L - n1;
-        const uint32_t bm1 = ((1u << n1) - 1u) * 0x01010101u, bm2 = ((1u << n2) - 1u) * 0x01010101u;
-        for (uint32_t r = rb; r < re; ++r) {
-            // the row's words for every layer in one scalar load
-            const uint32_t *info = rk_info + size_t(r) * 16;
-            uint32_t wv[LMAX];
+        // the row's words: J (| unreachable << 31) per layer, then R =
+        // (0x80 + rank) in every byte per layer; the next row's are loaded
+        // while this one is computed
+        uint32_t jn[LMAX], rn[LMAX];
+        if (rb < re) {
+            const uint32_t *info = rk_info + size_t(rb) * 32;
 #pragma unroll
-            for (int l = 0; l < LMAX; ++l) wv[l] = info[l];
-            uint32_t m1[G], m2[G];
+            for (int l = 0; l < LMAX; ++l) {
+                jn[l] = info[l];
+                rn[l] = info[16 + l];
+            }
+        }
+        for (uint32_t r = rb; r < re; ++r) {
+            uint32_t jw[LMAX], rw[LMAX];
+#pragma unroll
+            for (int l = 0; l < LMAX; ++l) {
+                jw[l] = jn[l];
+                rw[l] = rn[l];
+            }
+            if (r + 1 < re) {
+                const uint32_t *info = rk_info + size_t(r + 1) * 32;
+#pragma unroll
+                for (int l = 0; l < LMAX; ++l) {
+                    jn[l] = info[l];
+                    rn[l] = info[16 + l];
+                }
+            }
+            uint32_t m1[G], m2[G];                 // layers 0..7, 8..15: bit l of each byte
 #pragma unroll
             for (int g = 0; g < G; ++g) m1[g] = m2[g] = 0;
 #pragma unroll
             for (int l = 0; l < LMAX; ++l) {
-                if (uint32_t(l) < L) {
-                    const uint32_t w = wv[l];
-                    if (w & kRankInvalid) {
-#pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            if (l < 8) m1[g] = (m1[g] >> 1) & 0x7F7F7F7Fu;
-                            else m2[g] = (m2[g] >> 1) & 0x7F7F7F7Fu;
-                        }
-                    } else {
-                        const uint32_t J = (w >> 8) & 0xFFFFu;
-                        const uint32_t R = (0x80u + (w & 0xFFu)) * 0x01010101u;
+                if (NL > 0 || uint32_t(l) < L) {
+                    const uint32_t w = jw[l];
+                    if (ALLV || !(w & kRankInvalid)) {
+                        const uint32_t J = w & 0xFFFFu;
                         if (J != jc[l]) {
                             jc[l] = J;
                             const uint2 *bg = reinterpret_cast<const uint2 *>(bytes + l * (ngrp + 1) * 2);
@@ -236,13 +273,14 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
                                 cs[l][g] = __builtin_amdgcn_alignbyte(q1.y, q0.y, sh);
                             }
                         }
+                        const uint32_t kBit = 0x01010101u << (l & 7);       // l is unrolled: a constant
 #pragma unroll
                         for (int g = 0; g < G; ++g) {
-                            const uint32_t x = R - ca[l][g];
+                            const uint32_t x = rw[l] - ca[l][g];
                             const uint32_t y = x - cs[l][g];
-                            const uint32_t occ = ~x | y;           // bit 7 of each byte: occupied
-                            if (l < 8) m1[g] = (occ & 0x80808080u) | ((m1[g] >> 1) & 0x7F7F7F7Fu);
-                            else m2[g] = (occ & 0x80808080u) | ((m2[g] >> 1) & 0x7F7F7F7Fu);
+                            const uint32_t occ = (~x | y) >> (7 - (l & 7));   // occupied: bit l & 7
+                            if (l < 8) m1[g] = (occ & kBit) | (m1[g] & ~kBit);
+                            else m2[g] = (occ & kBit) | (m2[g] & ~kBit);
                         }
                     }
                 }
@@ -250,11 +288,9 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             uint16_t *dst = eacc + size_t(r) * nphi;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const uint32_t a1 = (m1[g] >> (8 - n1)) & bm1;
-                const uint32_t a2 = n2 ? (m2[g] >> (8 - n2)) & bm2 : 0u;
                 uint2 out;
-                out.x = __builtin_amdgcn_perm(a2, a1, 0x05010400u);
-                out.y = __builtin_amdgcn_perm(a2, a1, 0x07030602u);
+                out.x = __builtin_amdgcn_perm(m2[g], m1[g], 0x05010400u);
+                out.y = __builtin_amdgcn_perm(m2[g], m1[g], 0x07030602u);
                 *reinterpret_cast<uint2 *>(dst + 256u * g + 4u * lane) = out;
             }
         }
@@ -263,17 +299,17 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
 
 namespace {
 
-template <int G, int LMAX>
+template <int G, int NL, bool ALLV>
 void launch_rank_g(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint32_t n_tiles, uint32_t run,
                    uint32_t runs, uint32_t n_items, size_t lds, uint16_t *acc, hipStream_t s)
 {
     const hough_grid_spec &g = c->spec;
     if (bounds)
-        hipLaunchKernelGGL((k_vote_rank<G, LMAX, true>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer, h->phi,
-                           h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
+        hipLaunchKernelGGL((k_vote_rank<G, NL, ALLV, true>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer,
+                           h->phi, h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
                            g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
     else
-        hipLaunchKernelGGL((k_vote_rank<G, LMAX, false>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer,
+        hipLaunchKernelGGL((k_vote_rank<G, NL, ALLV, false>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer,
                            h->phi, h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
                            g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
 }
@@ -282,10 +318,14 @@ template <int G>
 void launch_rank(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint32_t n_tiles, uint32_t run,
                  uint32_t runs, uint32_t n_items, size_t lds, uint16_t *acc, hipStream_t s)
 {
-    if (c->spec.n_layers <= 10)
-        launch_rank_g<G, 10>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
+    // the ten-layer detector of every workload here gets exact-count
+    // instances; other layer counts the general one
+    if (c->spec.n_layers == 10 && c->all_valid)
+        launch_rank_g<G, 10, true>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
+    else if (c->spec.n_layers == 10)
+        launch_rank_g<G, 10, false>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
     else
-        launch_rank_g<G, 16>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
+        launch_rank_g<G, 0, false>(c, bounds, h, vec, n_tiles, run, runs, n_items, lds, acc, s);
 }
 
 size_t rank_lds_bytes(const hough_ctx *c, bool bounds)
@@ -308,7 +348,7 @@ void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, 
     const uint32_t L = g.n_layers;
     const uint32_t wmask = (1u << shift) - 1u;
     const uint32_t n_tiles = (rows + kRankTileRows - 1) / kRankTileRows;
-    info.assign(size_t(rows) * 16, 0u);
+    info.assign(size_t(rows) * 32, 0u);
     sorted.assign(size_t(n_tiles) * L * kRankSortStride, 0xFFFFFFFFu);
     std::vector<uint32_t> f;
     for (uint32_t t = 0; t < n_tiles; ++t) {
@@ -322,7 +362,8 @@ void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, 
                 const uint32_t o = O[size_t(l) * rows + r];
                 const uint32_t rank = uint32_t(std::lower_bound(f.begin(), f.end(), o & wmask) - f.begin());
                 const uint32_t J = o >> shift;
-                info[size_t(r) * 16 + l] = rank | (J << 8) | (V[size_t(l) * rows + r] ? 0u : kRankInvalid);
+                info[size_t(r) * 32 + l] = J | (V[size_t(l) * rows + r] ? 0u : kRankInvalid);
+                info[size_t(r) * 32 + 16 + l] = (0x80u + rank) * 0x01010101u;
             }
         }
     }

@@ -37,7 +37,8 @@ def vote_space():
 
 
 def peak_space():
-    return [dict(peak_rows=r) for r in (2, 4, 8, 16, 32, 64)]
+    return ([dict(peak_algo=2, peak_rows=r) for r in (16, 32, 64, 128)] +
+            [dict(peak_algo=1, peak_rows=r) for r in (2, 4, 8, 16, 32, 64)])
 
 
 def rz_space():

@@ -241,6 +241,67 @@ def test_rank_vote_form(H, kw, items):
             check_event(H, tab, res, batch, e)
 
 
+PEAK_SPECS = [dict(n_phi=256, n_qpt=16), dict(n_phi=512, n_qpt=300), dict(n_phi=1024, n_qpt=129),
+              dict(n_phi=256, n_qpt=1), dict(n_phi=512, n_qpt=2, threshold=0),
+              dict(n_phi=256, n_qpt=70, threshold=0), dict(n_phi=512, n_qpt=33, threshold=11),
+              dict(n_phi=1024, n_qpt=5, threshold=17)]
+
+
+@pytest.mark.parametrize("kw", PEAK_SPECS)
+@pytest.mark.parametrize("tuning", [dict(peak_algo=1), dict(peak_algo=2), dict(peak_algo=2, peak_rows=1),
+                                    dict(peak_algo=2, peak_rows=3), dict(peak_algo=2, peak_rows=4096)])
+def test_peak_forms(H, kw, tuning):
+    """The row-window peak form (a wavefront strip of rows in registers,
+    neighbours across lanes by wave rotates) and the LDS tile form against
+    the oracle: one-row and two-row grids, strips of 1, 3 and all rows
+    (ragged last strips), thresholds 0 (every plateau cell), 11 and 17 (no
+    peaks), on ragged events and the adversarial layer layouts."""
+    spec = small_spec(n_z0=0, n_cot=0, **kw)
+    tab = oracle.Tables(spec)
+    for batch in (ragged_batch(), gap_layout_batch(spec["n_phi"])):
+        res = run_gpu(H, spec, batch, tuning=tuning, rz=False)
+        for e in range(batch.n_events):
+            check_event(H, tab, res, batch, e)
+
+
+@pytest.mark.parametrize("peak_algo", [1, 2])
+def test_peak_capacity_overflow_both_forms(H, peak_algo):
+    """A peak list shorter than the peaks: the offsets still count every
+    peak, and the stored prefix equals the full run's."""
+    spec = small_spec(n_phi=512, n_qpt=40, n_z0=0, n_cot=0, threshold=0)
+    batch = ragged_batch()
+    t = dict(peak_algo=peak_algo, peak_rows=7)
+    full = run_gpu(H, spec, batch, tuning=t, rz=False)
+    total = int(H.offsets_numpy(full["poff"])[-1])
+    cap = total // 3 + 5
+    res = run_gpu(H, spec, batch, tuning=t, rz=False, peak_capacity=cap)
+    np.testing.assert_array_equal(H.offsets_numpy(res["poff"]), H.offsets_numpy(full["poff"]))
+    np.testing.assert_array_equal(H.peaks_numpy(res["pk"], res["poff"])[:cap],
+                                  H.peaks_numpy(full["pk"], full["poff"])[:cap])
+
+
+def test_unaligned_accumulator_peaks_take_the_tile_form(H):
+    """An accumulator 4- but not 8-byte aligned: the row-window form needs
+    aligned rows, so the peak search takes the LDS tile form; results equal
+    the oracle's."""
+    import torch
+    spec = small_spec(n_phi=256, n_qpt=24, n_z0=0, n_cot=0)
+    batch = ragged_batch()
+    ctx = H.HoughContext(spec, max_events=batch.n_events, max_hits=batch.n_hits)
+    hits = H.DeviceHits.from_batch(batch)
+    base = ctx.new_acc(batch.n_events + 1).view(-1)
+    acc = base[2:2 + batch.n_events * ctx.cells].view(batch.n_events, -1)
+    assert acc.data_ptr() % 8
+    ctx.vote(hits, acc)
+    pk, poff = ctx.peaks(acc, batch.n_events)
+    torch.cuda.synchronize()
+    tab = oracle.Tables(spec)
+    for e in range(batch.n_events):
+        ev = batch.event(e)
+        _, opk, _ = oracle.run_event(tab, ev.layer, ev.phi, ev.z, with_rz=False)
+        np.testing.assert_array_equal(H.peaks_numpy(pk, poff, e), opk.astype(H.PEAK_DTYPE), err_msg=f"event {e}")
+
+
 def test_unaligned_hit_arrays_and_accumulator(H):
     """Hit arrays that start one element past an aligned address and an
     accumulator that is 4- but not 8-byte aligned take the scalar load paths
