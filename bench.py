@@ -374,10 +374,27 @@ def bench_batched(H, torch, reps=5):
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 TRAFFIC_KERNELS = {
-    # bench name: (rocprofv3 kernel-name prefix, source file, workload)
-    "rz_vote": ("hough::k_rz_vote", "paper_1310_7556_amd/csrc/k_rz.hip", "c2_single_1ktrk_rz"),
+    # bench name: (rocprofv3 kernel-name prefix, source file, workload); the
+    # probe's largest dispatch of a prefix is the named workload's
+    "rz_vote": ("hough::k_rz_vote_fast", "paper_1310_7556_amd/csrc/k_rz.hip", "c2_single_1ktrk_rz"),
     "vote_direct": ("hough::k_vote_direct", "paper_1310_7556_amd/csrc/k_vote_direct.hip", "c4_batch_4096"),
+    "vote_rank_tile": ("hough::k_vote_rank<2, 10, true, false>", "paper_1310_7556_amd/csrc/k_vote_rank.hip",
+                       "c4_batch_4096"),
+    "vote_rank_event": ("hough::k_vote_rank<2, 10, true, true>", "paper_1310_7556_amd/csrc/k_vote_rank.hip",
+                        "c4_batch_4096"),
+    "vote_bounds": ("hough::k_vote_bounds", "paper_1310_7556_amd/csrc/k_vote_direct.hip", "c4_batch_4096"),
+    "peaks_count": ("hough::(anonymous namespace)::k_peaks_rows<8, false>",
+                    "paper_1310_7556_amd/csrc/k_peaks_rows.hip", "c4_batch_4096"),
+    "peaks_write": ("hough::(anonymous namespace)::k_peaks_rows<8, true>",
+                    "paper_1310_7556_amd/csrc/k_peaks_rows.hip", "c4_batch_4096"),
 }
+# SQ counters of the counter profiles: two passes of at most 8 SQ counters
+COUNTER_PASSES = (
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAIT_ANY "
+    "SQ_ACTIVE_INST_VALU",
+    "SQ_INSTS_VMEM SQ_INSTS_LDS_ATOMIC SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT SQ_WAIT_INST_LDS "
+    "SQ_ACTIVE_INST_LDS SQ_INSTS_BRANCH SQ_INST_CYCLES_SALU",
+)
 
 
 def source_sha(rel):
@@ -399,6 +416,7 @@ def traffic_probe(H, torch):
     name = "c2_single_1ktrk_rz"
     spec, ev = synth.grid_spec(name), synth.gen_config(name)
     ctx = H.HoughContext(spec, max_events=1, max_hits=ev.n_hits)
+    log(f"probe: c2 tuning {apply_cached_tuning(ctx, torch, spec, 1, ev.n_hits)}")
     hits = H.DeviceHits.from_batch(ev)
     acc = ctx.vote(hits)
     pk, poff = ctx.peaks(acc, 1, capacity=ctx.cells)
@@ -410,11 +428,55 @@ def traffic_probe(H, torch):
     spec, batch = synth.grid_spec(name), synth.gen_config(name)
     E = batch.n_events
     ctx = H.HoughContext(spec, max_events=E, max_hits=batch.n_hits)
+    log(f"probe: c4 tuning {apply_cached_tuning(ctx, torch, spec, E, batch.n_hits)}")
     hits = H.DeviceHits.from_batch(batch)
     acc = ctx.vote(hits)
     ctx.peaks(acc, E, capacity=E * ctx.cells)
     torch.cuda.synchronize()
     log("probe: done")
+
+
+def summarize_counters(paths):
+    """Per-dispatch SQ counter totals (summed over the XCDs' rows) of the
+    probe's kernels from rocprofv3 counter CSVs, as a markdown table of the
+    largest dispatch of each TRAFFIC_KERNELS prefix, with derived rates."""
+    import csv
+    disp = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"][5:] if r["Kernel_Name"].startswith("void ") else r["Kernel_Name"]
+            d = disp.setdefault((path, r["Dispatch_Id"]), dict(name=name, grid=int(r["Grid_Size"]),
+                                                               wg=int(r["Workgroup_Size"]), c={}))
+            d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    rows = {}
+    for label, (prefix, _, workload) in TRAFFIC_KERNELS.items():
+        merged = {}
+        for path in paths:
+            cands = [d for (p, _), d in disp.items() if p == path and d["name"].startswith(prefix)]
+            if cands:
+                big = max(cands, key=lambda d: d["grid"])
+                merged.update(big["c"])
+                merged["_grid"], merged["_wg"] = big["grid"], big["wg"]
+        if merged:
+            rows[label] = (workload, merged)
+    names = sorted({k for _, c in rows.values() for k in c if not k.startswith("_")})
+    print("| kernel (workload) | " + " | ".join(names) + " |")
+    print("|---|" + "---|" * len(names))
+    for label, (wl, c) in rows.items():
+        print(f"| {label} ({wl}) | " + " | ".join(f"{c[n]:.4g}" if n in c else "" for n in names) + " |")
+    print()
+    for label, (wl, c) in rows.items():
+        out = []
+        if "SQ_WAVE_CYCLES" in c and "SQ_WAIT_ANY" in c:
+            out.append(f"waiting {c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.2f} of wave cycles")
+        if "SQ_BUSY_CYCLES" in c and "SQ_INSTS_VALU" in c:
+            # VALU wave-instructions per SIMD per busy cycle (4 cycles each at full rate)
+            out.append(f"VALU {c['SQ_INSTS_VALU']:.3g} wave-instr")
+        if "SQ_INSTS_LDS_ATOMIC" in c:
+            out.append(f"LDS atomics {c['SQ_INSTS_LDS_ATOMIC']:.3g} wave-instr")
+        if "SQ_WAVES" in c:
+            out.append(f"{c['SQ_WAVES']:.0f} waves, grid {c['_grid']}, workgroup {c['_wg']}")
+        print(f"* {label}: " + "; ".join(out))
 
 
 def summarize_traffic(fetch_csv, write_csv):
@@ -671,9 +733,16 @@ def main():
                     help="run the copy/c2/c4 kernels once each (for rocprofv3 --pmc runs) and exit")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic file from two rocprofv3 counter CSVs and exit")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the c5 serving sweep (for a kernel trace of it) and print its JSON")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
+                    help="print the SQ counters of the probe's kernels from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: events are independent, so more GPUs would "
@@ -685,6 +754,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.traffic_probe:
         traffic_probe(H, torch)
+        return
+    if args.serving_only:
+        from paper_1310_7556_amd import serve
+        print(json.dumps(serve.bench_serving(H, torch, log=log)))
         return
 
     log("c2 single-event steps ...")

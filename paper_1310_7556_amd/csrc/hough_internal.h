@@ -136,11 +136,11 @@ struct PeakScratch {
 };
 PeakScratch ctx_peak_scratch(hough_ctx *c);
 // Row-window peak form (k_peaks_rows.hip): cells per lane (4, 8 or 16)
-// when it applies to this context and accumulator, else 0; rows per
-// wavefront strip; one pass (count or write) over n_events accumulators
-// with the tile counts and offsets of ps.
+// when it applies to this context, accumulator and batch size, else 0;
+// rows per wavefront strip; one pass (count or write) over n_events
+// accumulators with the tile counts and offsets of ps.
 constexpr uint32_t kPeakThreads = 256;
-uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc);
+uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc, uint32_t n_events);
 uint32_t peak_rows_strip(const hough_ctx *c);
 hipError_t launch_peaks_rows_pass(hough_ctx *c, bool write, const uint16_t *acc, uint32_t n_events,
                                   hough_peak *peaks, uint64_t capacity, const PeakScratch &ps, hipStream_t s);

@@ -493,7 +493,7 @@ uint32_t fit_rows(const hough_ctx *c, bool vec)
 
 uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc)
 {
-    if (peak_rows_cells_per_lane(c, acc)) {
+    if (peak_rows_cells_per_lane(c, acc, n_events)) {
         const uint32_t R = peak_rows_strip(c);
         return uint64_t(n_events) * ((c->spec.n_qpt + R - 1) / R);
     }
@@ -517,7 +517,7 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
     hipError_t err;
     KernelTimer t;
     t.name = nullptr;
-    if (peak_rows_cells_per_lane(c, acc)) {
+    if (peak_rows_cells_per_lane(c, acc, n_events)) {
         const uint32_t R = peak_rows_strip(c);
         const uint32_t n_strips = (c->spec.n_qpt + R - 1) / R;
         if (n_events == 0)

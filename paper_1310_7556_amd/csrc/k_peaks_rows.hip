@@ -270,7 +270,12 @@ void launch_rows(bool write, uint32_t blocks, size_t lds, hipStream_t s, const u
 
 }  // namespace
 
-uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc)
+uint32_t peak_rows_strip(const hough_ctx *c)
+{
+    return std::min(c->tun.peak_rows ? c->tun.peak_rows : 16u, c->spec.n_qpt);
+}
+
+uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc, uint32_t n_events)
 {
     if (c->tun.peak_algo == 1 || c->spec.n_d0 != 1) return 0;
     const uint32_t C = c->spec.n_phi / 64;
@@ -278,18 +283,21 @@ uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc)
     const uintptr_t align = C == 4 ? 8 : 16;
     if (reinterpret_cast<uintptr_t>(acc) % align != 0) return 0;
     if (size_t(kPeakThreads / 64) * 64 * C * 8 > c->max_lds) return 0;
+    // by default only when the strips (one wave each) fill the chip about
+    // twice: a single event has few strips, and the tile form's many small
+    // workgroups then finish sooner
+    if (c->tun.peak_algo == 0) {
+        const uint32_t R = peak_rows_strip(c);
+        const uint64_t strips = uint64_t(n_events) * ((c->spec.n_qpt + R - 1) / R);
+        if (strips < uint64_t(c->n_cu) * 8) return 0;
+    }
     return C;
-}
-
-uint32_t peak_rows_strip(const hough_ctx *c)
-{
-    return std::min(c->tun.peak_rows ? c->tun.peak_rows : 32u, c->spec.n_qpt);
 }
 
 hipError_t launch_peaks_rows_pass(hough_ctx *c, bool write, const uint16_t *acc, uint32_t n_events,
                                   hough_peak *peaks, uint64_t capacity, const PeakScratch &ps, hipStream_t s)
 {
-    const uint32_t C = peak_rows_cells_per_lane(c, acc);
+    const uint32_t C = peak_rows_cells_per_lane(c, acc, n_events);
     const uint32_t R = peak_rows_strip(c);
     const uint32_t n_strips = (c->spec.n_qpt + R - 1) / R;
     const uint64_t n_tiles = uint64_t(n_events) * n_strips;
