@@ -144,10 +144,21 @@ def bench_single(H, torch, steps, warmup):
         out["roofline"] = dict(kernel=dom, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS,
                                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 5), traffic=recorded_traffic(dom))
     out["rz_votes_per_s"] = rz_votes / (ms * 1e-3)
-    # k_rz_vote_fast issues one LDS atomic add per (member, cot bin) vote
+    # k_rz_vote_fast issues one LDS atomic add per (member, cot bin) vote of
+    # the members that can vote in range in a 64-cot pass (the others are
+    # skipped, their votes would all land in the trash counter); the count
+    # of those atomics comes from the SQ counters in profiles/ (64 lanes
+    # per SQ_INSTS_LDS_ATOMIC wave-instruction) while the kernel source is
+    # unchanged, else it is not reported
     t_rz = kernel_avg_ms(times, "rz_vote") * 1e-3
-    out["atomics"] = dict(kernel="rz_vote", space="lds", per_launch=rz_votes, per_s=rz_votes / t_rz,
-                          peak_estimate=LDS_ATOMIC_PEAK, frac=round(rz_votes / t_rz / LDS_ATOMIC_PEAK, 5))
+    sq = recorded_counters("rz_vote")
+    counted = int(sq["SQ_INSTS_LDS_ATOMIC"] * 64) if sq and "SQ_INSTS_LDS_ATOMIC" in sq else None
+    out["atomics"] = dict(kernel="rz_vote", space="lds", votes_algorithmic=rz_votes,
+                          per_launch_counted=counted,
+                          per_s=(counted / t_rz) if counted else None, peak_estimate=LDS_ATOMIC_PEAK,
+                          frac=round(counted / t_rz / LDS_ATOMIC_PEAK, 5) if counted else None,
+                          valu_wave_instr_counted=int(sq["SQ_INSTS_VALU"]) if sq and "SQ_INSTS_VALU" in sq
+                          else None)
     return out, (spec, ev)
 
 
@@ -373,16 +384,16 @@ def bench_batched(H, torch, reps=5):
 # source file, and the bench reports `traffic` only while it still matches.
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sq_counters.json")
 TRAFFIC_KERNELS = {
     # bench name: (rocprofv3 kernel-name prefix, source file, workload); the
     # probe's largest dispatch of a prefix is the named workload's
     "rz_vote": ("hough::k_rz_vote_fast", "paper_1310_7556_amd/csrc/k_rz.hip", "c2_single_1ktrk_rz"),
-    "vote_direct": ("hough::k_vote_direct", "paper_1310_7556_amd/csrc/k_vote_direct.hip", "c4_batch_4096"),
+    "vote_direct": ("hough::k_vote_direct", "paper_1310_7556_amd/csrc/k_vote_direct.hip", "c2_single_1ktrk_rz"),
     "vote_rank_tile": ("hough::k_vote_rank<2, 10, true, false>", "paper_1310_7556_amd/csrc/k_vote_rank.hip",
                        "c4_batch_4096"),
     "vote_rank_event": ("hough::k_vote_rank<2, 10, true, true>", "paper_1310_7556_amd/csrc/k_vote_rank.hip",
                         "c4_batch_4096"),
-    "vote_bounds": ("hough::k_vote_bounds", "paper_1310_7556_amd/csrc/k_vote_direct.hip", "c4_batch_4096"),
     "peaks_count": ("hough::(anonymous namespace)::k_peaks_rows<8, false>",
                     "paper_1310_7556_amd/csrc/k_peaks_rows.hip", "c4_batch_4096"),
     "peaks_write": ("hough::(anonymous namespace)::k_peaks_rows<8, true>",
@@ -412,6 +423,8 @@ def traffic_probe(H, torch):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+    from paper_1310_7556_amd import tune
+    log(f"probe: device {tune.device_name(torch)}")
     log("probe: c2 step")
     name = "c2_single_1ktrk_rz"
     spec, ev = synth.grid_spec(name), synth.gen_config(name)
@@ -438,8 +451,9 @@ def traffic_probe(H, torch):
 
 def summarize_counters(paths):
     """Per-dispatch SQ counter totals (summed over the XCDs' rows) of the
-    probe's kernels from rocprofv3 counter CSVs, as a markdown table of the
-    largest dispatch of each TRAFFIC_KERNELS prefix, with derived rates."""
+    probe's kernels from rocprofv3 counter CSVs: the largest dispatch of each
+    TRAFFIC_KERNELS prefix, written to COUNTERS_FILE (with each kernel's
+    source hash) and printed as a markdown table with derived rates."""
     import csv
     disp = {}
     for path in paths:
@@ -459,6 +473,13 @@ def summarize_counters(paths):
                 merged["_grid"], merged["_wg"] = big["grid"], big["wg"]
         if merged:
             rows[label] = (workload, merged)
+    record = {label: dict(workload=wl, source=TRAFFIC_KERNELS[label][1],
+                          sha256=source_sha(TRAFFIC_KERNELS[label][1]),
+                          grid=c["_grid"], workgroup=c["_wg"],
+                          counters={k: v for k, v in c.items() if not k.startswith("_")})
+              for label, (wl, c) in rows.items()}
+    with open(COUNTERS_FILE, "w") as fh:
+        json.dump(record, fh, indent=1)
     names = sorted({k for _, c in rows.values() for k in c if not k.startswith("_")})
     print("| kernel (workload) | " + " | ".join(names) + " |")
     print("|---|" + "---|" * len(names))
@@ -513,6 +534,17 @@ def summarize_traffic(fetch_csv, write_csv):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def recorded_counters(name):
+    """SQ counters of kernel `name` from COUNTERS_FILE, or None when absent or
+    when its source has changed since they were taken."""
+    try:
+        with open(COUNTERS_FILE) as fh:
+            k = json.load(fh)[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    return k["counters"] if source_sha(k["source"]) == k["sha256"] else None
 
 
 def recorded_traffic(name):

@@ -50,7 +50,7 @@ void free_all(hough_ctx *c)
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
                     c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list,
                     c->d_scan_part, c->d_scan_off, c->d_dir_tab, c->d_cl_rank, c->d_cl_part,
-                    c->d_cl_part_off};
+                    c->d_cl_part_off, c->d_part_cnt, c->d_part_base};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : c->pending) {
@@ -241,6 +241,8 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
     const uint32_t L = spec->n_layers;
     c->n_peak_tiles = std::max<uint64_t>(uint64_t(E) * c->rows, E);
     c->scan_blocks_max = scan_blocks(c->n_peak_tiles);
+    // split_parts keeps E * K <= E + kSplitPartsPerCu * n_cu (K <= ceil(4 n_cu / E))
+    c->max_parts = uint64_t(E) + uint64_t(kSplitPartsPerCu) * c->n_cu;
     const size_t nb = buckets ? (size_t(1) << c->bucket_bits) + 1 : 0;
     const size_t ncand = rz ? size_t(E) * spec->rz_max_candidates : 0;
     const size_t rzh = rz ? size_t(c->n_cu) * kMaxRzWavesPerCu * spec->n_z0 : 0;
@@ -253,6 +255,8 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
               dev_alloc(&c->d_counters, 64) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&
               dev_alloc(&c->d_tile_off, c->n_peak_tiles + 1) && dev_alloc(&c->d_cand, ncand) &&
               dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh) &&
+              dev_alloc(&c->d_part_cnt, c->max_parts * kSplitBins) &&
+              dev_alloc(&c->d_part_base, c->max_parts * kSplitBins) &&
               dev_alloc(&c->d_gap_info, size_t(E) * L) && dev_alloc(&c->d_gap_list, H) &&
               dev_alloc(&c->d_scan_part, c->scan_blocks_max) && dev_alloc(&c->d_scan_off, c->scan_blocks_max + 1) &&
               dev_alloc(&c->d_dir_tab, size_t(E) * L * spec->n_phi) &&

@@ -84,6 +84,11 @@ struct hough_ctx {
     uint64_t *d_tile_off = nullptr;    // [max peak tiles + 1]
     uint32_t *d_cand = nullptr;        // [max_events * rz_max_candidates]
     uint32_t *d_cand_counts = nullptr; // [max_events]
+    // split forms of the per-event passes for batches of few events (K
+    // parts per event, E * K <= max_events + kSplitPartsPerCu * n_cu):
+    uint32_t *d_part_cnt = nullptr;    // [parts][kSplitBins] per-part counts
+    uint32_t *d_part_base = nullptr;   // [parts][kSplitBins] per-part starts
+    uint64_t max_parts = 0;
     uint32_t *d_rz_hist = nullptr;     // [rz blocks][n_z0] zeroed uint32 (rz slow path)
     uint4 *d_gap_info = nullptr;       // [max_events][L] gap vote: {mode, entries, list start, 0}
     uint2 *d_gap_list = nullptr;       // [max_hits] gap vote: per-layer hit or gap lists
@@ -144,6 +149,22 @@ uint32_t peak_rows_cells_per_lane(const hough_ctx *c, const uint16_t *acc, uint3
 uint32_t peak_rows_strip(const hough_ctx *c);
 hipError_t launch_peaks_rows_pass(hough_ctx *c, bool write, const uint16_t *acc, uint32_t n_events,
                                   hough_peak *peaks, uint64_t capacity, const PeakScratch &ps, hipStream_t s);
+// Split forms (k_bucket.hip, k_rz.hip): a batch of E events is cut into K
+// parts per event when E is small, so that a per-event pass runs on many
+// workgroups; K = 0 when the one-workgroup-per-event form is used.
+constexpr uint32_t kSplitPartsPerCu = 4;
+constexpr uint32_t kSplitMaxParts = 64;
+constexpr uint32_t kSplitBins = 17;      // layers (<= 16) or popcount levels 0..16
+inline uint32_t split_parts(const hough_ctx *c, uint32_t E)
+{
+    if (E == 0 || E >= 2u * uint32_t(c->n_cu) || !c->d_part_cnt) return 0;
+    const uint32_t K = (kSplitPartsPerCu * uint32_t(c->n_cu) + E - 1) / E;
+    return K < 2 ? 0 : (K > kSplitMaxParts ? kSplitMaxParts : K);
+}
+// The split forms' plan pass (k_bucket.hip): per event, the start of each of
+// n_bins bins and each part's first position per bin (bin_off may be null).
+hipError_t launch_split_plan(uint32_t n_events, uint32_t n_bins, uint32_t K, const uint32_t *part_cnt,
+                             uint32_t *part_base, uint32_t *bin_off, hipStream_t s);
 // Number of tiles the peak search of n_events accumulators at `acc` uses.
 uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc);
 // timed = false: no per-kernel timing (no HIP events are created)

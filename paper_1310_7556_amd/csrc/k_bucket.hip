@@ -56,6 +56,130 @@ k_bucket_layers(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ 
     }
 }
 
+// Split form of the layer sort for batches of few events: event e is cut
+// into K parts of consecutive hits, one 256-thread workgroup each.
+// k_layer_count counts a part's hits per layer (one ballot per layer per 64
+// hits, no atomics); k_split_plan (one wave per event) turns the parts'
+// counts into the event's layer offsets and each part's first position per
+// layer; k_layer_scatter places a part's hits in input order.  The result
+// is a stable counting sort, so the order inside a layer is the input order.
+constexpr uint32_t kSplitThreads = 256;
+
+__device__ __forceinline__ void part_range(const uint64_t *offs, uint32_t e, uint32_t k, uint32_t K, uint64_t n,
+                                           uint64_t &pb, uint64_t &pe)
+{
+    uint64_t b, end;
+    event_range(offs, e, n, b, end);
+    const uint64_t len = end - b;
+    pb = b + len * k / K;
+    pe = b + len * (k + 1) / K;
+}
+
+__global__ void __launch_bounds__(kSplitThreads)
+k_layer_count(const uint8_t *__restrict__ layer, const uint64_t *__restrict__ offs, uint64_t n_hits,
+              uint32_t n_layers, uint32_t K, uint32_t *__restrict__ part_cnt)
+{
+    __shared__ uint32_t wc[kSplitThreads / 64][kMaxLayers];
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    uint64_t pb, pe;
+    part_range(offs, blockIdx.x / K, blockIdx.x % K, K, n_hits, pb, pe);
+    uint32_t cnt[kMaxLayers];
+#pragma unroll
+    for (uint32_t q = 0; q < kMaxLayers; ++q) cnt[q] = 0;
+    for (uint64_t i0 = pb + wave * 64; i0 < pe; i0 += kSplitThreads) {
+        const uint64_t i = i0 + lane;
+        const uint32_t l = i < pe ? layer[i] : 0xFFu;
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxLayers; ++q)
+            if (q < n_layers) cnt[q] += uint32_t(__popcll(__ballot(l == q)));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxLayers; ++q) wc[wave][q] = cnt[q];
+    }
+    __syncthreads();
+    if (t < n_layers) {
+        uint32_t s = 0;
+        for (uint32_t w = 0; w < kSplitThreads / 64; ++w) s += wc[w][t];
+        part_cnt[size_t(blockIdx.x) * kSplitBins + t] = s;
+    }
+}
+
+// One wave per event: for each of the event's bins (layers) in order, the
+// bin's start is the sum of all earlier bins, and part k's first position
+// in bin v is the start plus the counts of parts 0..k-1 in v.  bin_off
+// receives the n_bins + 1 starts (relative to the event) when not null.
+__global__ void __launch_bounds__(64)
+k_split_plan(const uint32_t *__restrict__ part_cnt, uint32_t n_bins, uint32_t K, uint32_t *__restrict__ part_base,
+             uint32_t *__restrict__ bin_off)
+{
+    const uint32_t e = blockIdx.x, lane = threadIdx.x;
+    uint32_t run = 0;
+    for (uint32_t v = 0; v < n_bins; ++v) {
+        const uint32_t x = lane < K ? part_cnt[(size_t(e) * K + lane) * kSplitBins + v] : 0u;
+        uint32_t incl = x;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            incl += lane >= d ? y : 0u;
+        }
+        if (lane < K) part_base[(size_t(e) * K + lane) * kSplitBins + v] = run + incl - x;
+        if (bin_off && lane == 0) bin_off[size_t(e) * (n_bins + 1) + v] = run;
+        run += __shfl(incl, 63, 64);
+    }
+    if (bin_off && lane == 0) bin_off[size_t(e) * (n_bins + 1) + n_bins] = run;
+}
+
+template <bool WITH_Z>
+__global__ void __launch_bounds__(kSplitThreads)
+k_layer_scatter(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi, const int32_t *__restrict__ z,
+                const uint64_t *__restrict__ offs, uint64_t n_hits, uint32_t n_layers, uint32_t K,
+                const uint32_t *__restrict__ part_base, uint32_t *__restrict__ out_phi, int32_t *__restrict__ out_z)
+{
+    __shared__ uint32_t wc[kSplitThreads / 64][kMaxLayers];
+    __shared__ uint32_t base[kMaxLayers];
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const uint32_t e = blockIdx.x / K;
+    uint64_t b, end, pb, pe;
+    event_range(offs, e, n_hits, b, end);
+    part_range(offs, e, blockIdx.x % K, K, n_hits, pb, pe);
+    if (t < n_layers) base[t] = part_base[size_t(blockIdx.x) * kSplitBins + t];
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    // rounds of 256 consecutive hits, wave w taking the w-th 64
+    for (uint64_t r0 = pb; r0 < pe; r0 += kSplitThreads) {
+        const uint64_t i = r0 + t;
+        const bool ok = i < pe;
+        const uint32_t l = ok ? layer[i] : 0xFFu;
+        const uint32_t ph = ok ? phi[i] : 0u;
+        const int32_t zz = WITH_Z && ok ? z[i] : 0;
+        uint32_t rank = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxLayers; ++q) {
+            if (q < n_layers) {
+                const uint64_t m = __ballot(l == q);
+                if (lane == 0) wc[wave][q] = uint32_t(__popcll(m));
+                if (l == q) rank = uint32_t(__popcll(m & lt));
+            }
+        }
+        __syncthreads();
+        if (l < n_layers) {
+            uint32_t pos = base[l] + rank;
+            for (uint32_t w = 0; w < wave; ++w) pos += wc[w][l];
+            out_phi[b + pos] = ph;
+            if (WITH_Z) out_z[b + pos] = zz;
+        }
+        __syncthreads();
+        if (t < n_layers) {
+            uint32_t s = 0;
+            for (uint32_t w = 0; w < kSplitThreads / 64; ++w) s += wc[w][t];
+            base[t] += s;
+        }
+        __syncthreads();
+    }
+}
+
 // Exclusive scan of n (<= 4 * blockDim) LDS counters in place; returns total.
 __device__ uint32_t block_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *tmp)
 {
@@ -155,6 +279,21 @@ hipError_t launch_bucket_layers(hough_ctx *c, const hough_hits *h, bool with_z, 
     if (h->n_events == 0) return hipSuccess;
     KernelTimer t;
     prof_begin(c, "bucket_layers", s, &t);
+    if (const uint32_t K = split_parts(c, h->n_events)) {
+        const uint32_t parts = h->n_events * K, L = c->spec.n_layers;
+        hipLaunchKernelGGL(k_layer_count, dim3(parts), dim3(kSplitThreads), 0, s, h->layer, h->event_offsets,
+                           h->n_hits, L, K, c->d_part_cnt);
+        hipError_t err = launch_split_plan(h->n_events, L, K, c->d_part_cnt, c->d_part_base, c->d_layer_off, s);
+        if (err != hipSuccess) return err;
+        if (with_z)
+            hipLaunchKernelGGL(k_layer_scatter<true>, dim3(parts), dim3(kSplitThreads), 0, s, h->layer, h->phi,
+                               h->z_um, h->event_offsets, h->n_hits, L, K, c->d_part_base, c->d_phi_a, c->d_z_a);
+        else
+            hipLaunchKernelGGL(k_layer_scatter<false>, dim3(parts), dim3(kSplitThreads), 0, s, h->layer, h->phi,
+                               h->z_um, h->event_offsets, h->n_hits, L, K, c->d_part_base, c->d_phi_a, c->d_z_a);
+        prof_end(c, s, &t);
+        return hipGetLastError();
+    }
     if (with_z)
         hipLaunchKernelGGL(k_bucket_layers<true>, dim3(h->n_events), dim3(1024), 0, s, h->layer,
                            h->phi, h->z_um, h->event_offsets, h->n_hits, c->spec.n_layers,
@@ -164,6 +303,14 @@ hipError_t launch_bucket_layers(hough_ctx *c, const hough_hits *h, bool with_z, 
                            h->phi, h->z_um, h->event_offsets, h->n_hits, c->spec.n_layers,
                            c->d_phi_a, c->d_z_a, c->d_layer_off);
     prof_end(c, s, &t);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_plan(uint32_t n_events, uint32_t n_bins, uint32_t K, const uint32_t *part_cnt,
+                             uint32_t *part_base, uint32_t *bin_off, hipStream_t s)
+{
+    if (n_events == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_plan, dim3(n_events), dim3(64), 0, s, part_cnt, n_bins, K, part_base, bin_off);
     return hipGetLastError();
 }
 

@@ -18,18 +18,19 @@
 //      wave prefix over window lengths flattens all layers' scanned hits,
 //      and one ballot-compacted pass copies the members' z (grouped by layer)
 //      into LDS;
-//   2. per cot bin, per member: u = z - (Z + z0_lo) in uint32, bin by one
-//      multiply-high (BinMagic, no shift where that is exact), which maps
-//      every u >= span past the last bin into a trash counter, and an LDS
-//      atomic add on a lane-private packed counter (8- or 16-bit) whose
-//      return value gives the running count without a read-modify-write
-//      chain; members are padded to a multiple of 4 with ones that never
-//      vote;
+//   2. per pass of 64 cot bins (one per lane), the members that can vote in
+//      range are compacted again; per member: u = z - (Z + z0_lo) in
+//      uint32, bin by one multiply-high (BinMagic, no shift where that is
+//      exact), which maps every u >= span past the last bin into a trash
+//      counter, and an LDS atomic add on a lane-private packed counter (4-,
+//      8- or 16-bit) whose return value gives the running count without a
+//      read-modify-write chain;
 //   3. the counters are cleared wholesale with 16-byte stores.
-// A candidate with more members than the LDS list or the counter width
-// holds takes the slow path: a uint32 histogram in global scratch, one cot
-// bin at a time.  k_rz_vote is the general kernel (64-bit arithmetic) for
-// specs outside the fast path's range conditions.
+// A candidate with more members than the LDS list holds, or whose 4- or
+// 8-bit counter overflowed, is marked in its record and recomputed by
+// k_rz_redo on the exact slow path: a uint32 histogram in global scratch,
+// one cot bin at a time.  k_rz_vote is the general kernel (64-bit
+// arithmetic) for specs outside the fast path's range conditions.
 #include <type_traits>
 
 #include "fastdiv.h"
@@ -313,7 +314,7 @@ __global__ void __launch_bounds__(64) k_rz_vote(RzParams P)
 // LDS layout of the fast kernel, in dwords: counters, the layer windows,
 // the pass boundary table, then two member lists (all members of the
 // candidate; those of the current pass), each z values then layer bytes for
-// mcap members plus up to 7 padding ones, 16-byte aligned.
+// mcap members and 8 spare slots, 16-byte aligned.
 __host__ __device__ inline uint32_t rz_list_z_dwords(uint32_t mcap) { return (mcap + 8 + 3) & ~3u; }
 __host__ __device__ inline uint32_t rz_list_dwords(uint32_t mcap)
 {
@@ -376,7 +377,7 @@ k_rz_vote_fast(RzParams P)
         // so that they arrive with the member search's loads: the table is
         // [k][cot][16 layers], so they are 64 contiguous bytes (4 loads; a
         // lane past the last cot bin reads the last one).  Layers >=
-        // n_layers hold 0, which the padding layer 15 needs.
+        // n_layers hold 0.
         const int32_t *zrow = P.Zl + size_t(k) * P.n_cot * kMaxLayers;
         uint32_t zr[kMaxLayers], zn[kMaxLayers];
         auto load_rows = [&](uint32_t jj, uint32_t (&zz)[kMaxLayers]) {
@@ -447,7 +448,10 @@ k_rz_vote_fast(RzParams P)
             int32_t zv = 0;
             uint32_t ls = 0;
             if (gi < T) {
-                for (uint32_t q = 0; q < nl; ++q) ls = lay[q] <= gi ? q : ls;
+                // the hit's layer: the last window starting at or before gi
+                // (starts are non-decreasing; lanes nl..15 hold T)
+#pragma unroll
+                for (uint32_t s = 8; s > 0; s >>= 1) ls += lay[ls + s] <= gi ? s : 0u;
                 const uint32_t local = gi - lay[ls];
                 const uint32_t l1 = lay[16 + ls];
                 const uint32_t h = local < l1 ? lay[32 + ls] + local : lay[48 + ls] + (local - l1);
@@ -470,9 +474,11 @@ k_rz_vote_fast(RzParams P)
         uint32_t best_c = 0, best_j = lane, best_b = 0;
         bool ovf = false;                  // a 4- or 8-bit counter of a real bin overflowed
         if (nm <= lim) {
-            // the next pass's (Z + z0_lo) values are loaded while the current
-            // one counts (one memory latency per candidate, not per pass)
-            for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 64) {
+            // One 64-cot pass: zc holds this pass's (Z + z0_lo) rows and zx
+            // receives the next pass's, loaded while this one counts (one
+            // memory latency per candidate, not per pass); consecutive passes
+            // swap the two sets instead of copying.
+            auto pass = [&](uint32_t j0, uint32_t (&zc)[kMaxLayers], uint32_t (&zx)[kMaxLayers]) {
                 const uint32_t j = j0 + lane;
                 const bool jv = j < P.n_cot;
                 // Members of this pass.  (Z + z0_lo) is monotone in the cot
@@ -496,7 +502,10 @@ k_rz_vote_fast(RzParams P)
                         zm = mz[m];
                         lm = ml[m];
                         const int32_t za = tb[lm], zb = tb[16 + lm];
-                        act = zm >= min(za, zb) && int64_t(zm) - int64_t(max(za, zb)) < int64_t(P.span);
+                        const int32_t mx = max(za, zb);
+                        // z - max < span as integers: true when z < max, else
+                        // the 32-bit difference is exact
+                        act = zm >= min(za, zb) && (zm < mx || uint64_t(uint32_t(zm - mx)) < P.span);
                     }
                     const uint64_t bal = __ballot(act);
                     const uint32_t pos = nq + __popcll(bal & ((1ull << lane) - 1ull));
@@ -506,27 +515,18 @@ k_rz_vote_fast(RzParams P)
                     }
                     nq += __popcll(bal);
                 }
-                // pad to a multiple of 4 with members that never vote: layer
-                // 15 is unused (n_layers < 16 on this path), so its (Z +
-                // z0_lo) register is 0, and z = 0xFFFFFFFF is then out of
-                // range for every cot bin
-                const uint32_t np4 = (nq + 3u) & ~3u;
-                if (lane < np4 - nq) {
-                    mzc[nq + lane] = -1;
-                    mlc[nq + lane] = uint8_t(kMaxLayers - 1);
-                }
                 __syncthreads();
                 // next pass's rows (after the last pass they are loaded and
                 // not used: the index is clamped, so the loads stay in bounds)
-                load_rows(j + 64, zn);
-                // all members in one flat loop, eight per step (a last step of
-                // four): 16-byte LDS reads give four z each, 4-byte reads
-                // their layers (so (Z + z0_lo) is a register-indexed move).  Per member: the
-                // bin b = min(mulhi(u, m), n_z0) of u = z - (Z + z0_lo) --
-                // the multiply-high maps every u >= span (out of range, a
-                // padding member, or a lane past the last cot bin whose
-                // result is dropped) to n_z0 or above, so those votes land in
-                // a trash counter past the last bin -- then the lane-private
+                load_rows(j + 64, zx);
+                // The members in one flat loop, eight per step, then steps of
+                // four, two and one for the rest: 16-byte LDS reads give four
+                // z each, 4-byte reads their layers (so (Z + z0_lo) is a
+                // register-indexed move).  Per member: the bin b of u = z -
+                // (Z + z0_lo) from the multiply-high -- every u >= span (out
+                // of range, or a lane past the last cot bin whose result is
+                // dropped) maps to n_z0 or above, so those votes land in a
+                // trash counter past the last bin -- then the lane-private
                 // packed counter atomic and the running maximum of the signed
                 // key (count - 1) * 2^16 - b over in-range votes (largest
                 // count wins, ties to the smallest bin)
@@ -535,24 +535,37 @@ k_rz_vote_fast(RzParams P)
                 // this lane's counter column (row stride 64 dwords)
                 uint32_t *col = hist + lane;
                 int32_t run = INT32_MIN;
-                // Q members per step (8, then one step of 4 for the rest)
+                // Q members per step, starting at member m (a multiple of Q)
                 auto step = [&](auto qc, uint32_t m) {
                     constexpr int Q = decltype(qc)::value;
-                    uint32_t zm[Q], lw[Q / 4];
+                    uint32_t zm[Q], lq[Q];
+                    if constexpr (Q >= 4) {
 #pragma unroll
-                    for (int g = 0; g < Q / 4; ++g) {
-                        const uint4 z4 = mz4[(m >> 2) + g];
-                        zm[4 * g] = z4.x;
-                        zm[4 * g + 1] = z4.y;
-                        zm[4 * g + 2] = z4.z;
-                        zm[4 * g + 3] = z4.w;
-                        lw[g] = uni(ml4[(m >> 2) + g]);
+                        for (int g = 0; g < Q / 4; ++g) {
+                            const uint4 z4 = mz4[(m >> 2) + g];
+                            zm[4 * g] = z4.x;
+                            zm[4 * g + 1] = z4.y;
+                            zm[4 * g + 2] = z4.z;
+                            zm[4 * g + 3] = z4.w;
+                            const uint32_t lw = uni(ml4[(m >> 2) + g]);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) lq[4 * g + i] = (lw >> (8 * i)) & 0xFFu;
+                        }
+                    } else if constexpr (Q == 2) {
+                        const uint2 z2 = reinterpret_cast<const uint2 *>(mzc)[m >> 1];
+                        zm[0] = z2.x;
+                        zm[1] = z2.y;
+                        const uint32_t lw = uni(ml4[m >> 2]) >> (8 * (m & 3u));
+                        lq[0] = lw & 0xFFu;
+                        lq[1] = (lw >> 8) & 0xFFu;
+                    } else {
+                        zm[0] = uint32_t(mzc[m]);
+                        lq[0] = uni(uint32_t(mlc[m]));
                     }
                     uint32_t b[Q], sh[Q], old[Q];
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        const uint32_t lq = (lw[q >> 2] >> (8 * (q & 3))) & 0xFFu;
-                        const uint32_t u = zm[q] - zr[lq];
+                        const uint32_t u = zm[q] - zc[lq[q]];
                         if (MUL == 2) {
                             // both factors below 2^24: the 24-bit multiply-high
                             b[q] = uint32_t((uint64_t(min(u, P.span24) & 0xFFFFFFu) * (P.bm & 0xFFFFFFu)) >> 32);
@@ -576,21 +589,27 @@ k_rz_vote_fast(RzParams P)
                     }
                 };
                 uint32_t m = 0;
-                for (; m + 8 <= np4; m += 8) step(std::integral_constant<int, 8>{}, m);
-                if (m < np4) step(std::integral_constant<int, 4>{}, m);
+                for (; m + 8 <= nq; m += 8) step(std::integral_constant<int, 8>{}, m);
+                if (m + 4 <= nq) {
+                    step(std::integral_constant<int, 4>{}, m);
+                    m += 4;
+                }
+                if (m + 2 <= nq) {
+                    step(std::integral_constant<int, 2>{}, m);
+                    m += 2;
+                }
+                if (m < nq) step(std::integral_constant<int, 1>{}, m);
                 const int32_t fld = (run + 0xFFFF) >> 16;
                 const uint32_t bc = run == INT32_MIN ? 0u : uint32_t(fld) + 1u;
                 const uint32_t bb = uint32_t((fld << 16) - run);
                 // a count of FIELD + 1 can only come from a vote that found
                 // its field full: the counter overflowed
                 if (BITS <= 8) ovf = ovf || bc > FIELD;
-#pragma unroll
-                for (uint32_t l = 0; l < kMaxLayers; ++l) zr[l] = zn[l];
                 // clear all counters, 16 bytes per lane per store; a store
                 // covers other lanes' columns, so every lane's counting must
                 // be finished first and the clear finished before the next
                 // cot bins are counted (nothing to clear after an empty pass)
-                if (np4) {
+                if (nq) {
                     __syncthreads();
                     uint4 *h4 = reinterpret_cast<uint4 *>(hist);
                     const uint32_t n4 = P.hw * 16;
@@ -599,6 +618,10 @@ k_rz_vote_fast(RzParams P)
                 }
                 __syncthreads();
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
+            };
+            for (uint32_t j0 = 0; j0 < P.n_cot; j0 += 128) {
+                pass(j0, zr, zn);
+                if (j0 + 64 < P.n_cot) pass(j0 + 64, zn, zr);
             }
         }
         // an overflowed count makes every result of this candidate suspect
@@ -708,6 +731,103 @@ k_rz_select(const uint2 *__restrict__ peaks, uint64_t peak_capacity, const uint6
     }
 }
 
+// Split form of the candidate selection for batches of few events: an
+// event's stored peaks are cut into K parts of consecutive peaks (256
+// threads each).  A peak's bin is 16 - min(popcount, 16), so ascending bins
+// are descending popcounts.  k_sel_count counts a part's peaks per bin (one
+// ballot per bin per 64 peaks); the split plan gives every bin's start and
+// each part's first position per bin, i.e. each peak's position in the
+// (popcount desc, cell asc) order; k_sel_write stores the peaks whose
+// position is below the event's cap, in that order.
+constexpr uint32_t kSelThreads = 256;
+
+__device__ __forceinline__ void sel_part(const uint64_t *poff, uint64_t peak_capacity, uint32_t e, uint32_t k,
+                                         uint32_t K, uint64_t &lo, uint64_t &hi, uint64_t &pb, uint64_t &pe)
+{
+    lo = min(poff[e], peak_capacity);
+    hi = min(max(poff[e + 1], poff[e]), peak_capacity);
+    const uint64_t n = hi - lo;
+    pb = lo + n * k / K;
+    pe = lo + n * (k + 1) / K;
+}
+
+__global__ void __launch_bounds__(kSelThreads)
+k_sel_count(const uint2 *__restrict__ peaks, uint64_t peak_capacity, const uint64_t *__restrict__ poff, uint32_t K,
+            uint32_t *__restrict__ part_cnt)
+{
+    __shared__ uint32_t wc[kSelThreads / 64][kSplitBins];
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    uint64_t lo, hi, pb, pe;
+    sel_part(poff, peak_capacity, blockIdx.x / K, blockIdx.x % K, K, lo, hi, pb, pe);
+    uint32_t cnt[kSplitBins];
+#pragma unroll
+    for (uint32_t q = 0; q < kSplitBins; ++q) cnt[q] = 0;
+    for (uint64_t i0 = pb + wave * 64; i0 < pe; i0 += kSelThreads) {
+        const uint64_t i = i0 + lane;
+        const uint32_t bin = i < pe ? 16u - min(peaks[i].y >> 16, 16u) : 0xFFu;
+#pragma unroll
+        for (uint32_t q = 0; q < kSplitBins; ++q) cnt[q] += uint32_t(__popcll(__ballot(bin == q)));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (uint32_t q = 0; q < kSplitBins; ++q) wc[wave][q] = cnt[q];
+    }
+    __syncthreads();
+    if (t < kSplitBins) {
+        uint32_t s = 0;
+        for (uint32_t w = 0; w < kSelThreads / 64; ++w) s += wc[w][t];
+        part_cnt[size_t(blockIdx.x) * kSplitBins + t] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kSelThreads)
+k_sel_write(const uint2 *__restrict__ peaks, uint64_t peak_capacity, const uint64_t *__restrict__ poff,
+            const uint64_t *__restrict__ roff, uint32_t cap, uint32_t K, const uint32_t *__restrict__ part_base,
+            uint32_t *__restrict__ cand)
+{
+    __shared__ uint32_t wc[kSelThreads / 64][kSplitBins];
+    __shared__ uint32_t base[kSplitBins];
+    const uint32_t t = threadIdx.x, lane = t & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const uint32_t e = blockIdx.x / K;
+    uint64_t lo, hi, pb, pe;
+    sel_part(poff, peak_capacity, e, blockIdx.x % K, K, lo, hi, pb, pe);
+    const uint32_t need = uint32_t(min(hi - lo, uint64_t(cap)));
+    if (t < kSplitBins) base[t] = part_base[size_t(blockIdx.x) * kSplitBins + t];
+    __syncthreads();
+    // nothing of this part is taken once every bin's next position is past the cap
+    uint32_t lowest = 0xFFFFFFFFu;
+    for (uint32_t q = 0; q < kSplitBins; ++q) lowest = min(lowest, base[q]);
+    if (lowest >= need) return;                     // uniform over the workgroup
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint32_t *out = cand + roff[e];
+    for (uint64_t r0 = pb; r0 < pe; r0 += kSelThreads) {
+        const uint64_t i = r0 + t;
+        const uint32_t bin = i < pe ? 16u - min(peaks[i].y >> 16, 16u) : 0xFFu;
+        uint32_t rank = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kSplitBins; ++q) {
+            const uint64_t m = __ballot(bin == q);
+            if (lane == 0) wc[wave][q] = uint32_t(__popcll(m));
+            if (bin == q) rank = uint32_t(__popcll(m & lt));
+        }
+        __syncthreads();
+        if (bin < kSplitBins) {
+            uint32_t pos = base[bin] + rank;
+            for (uint32_t w = 0; w < wave; ++w) pos += wc[w][bin];
+            if (pos < need) out[pos] = uint32_t(i - lo);
+        }
+        __syncthreads();
+        if (t < kSplitBins) {
+            uint32_t s = 0;
+            for (uint32_t w = 0; w < kSelThreads / 64; ++w) s += wc[w][t];
+            base[t] += s;
+        }
+        __syncthreads();
+    }
+}
+
 uint32_t rz_blocks(const hough_ctx *c)
 {
     const uint32_t w = c->tun.rz_waves_per_cu ? c->tun.rz_waves_per_cu : 8;
@@ -755,9 +875,20 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         return err;
     if (g.rz_max_candidates) {
         prof_begin(c, "rz_select", s, &t);
-        hipLaunchKernelGGL(k_rz_select, dim3(E), dim3(256), 0, s,
-                           reinterpret_cast<const uint2 *>(peaks), peak_capacity, poff, roff,
-                           g.rz_max_candidates, c->d_cand);
+        if (const uint32_t K = split_parts(c, E)) {
+            const uint2 *pk = reinterpret_cast<const uint2 *>(peaks);
+            hipLaunchKernelGGL(k_sel_count, dim3(E * K), dim3(kSelThreads), 0, s, pk, peak_capacity, poff, K,
+                               c->d_part_cnt);
+            if ((err = launch_split_plan(E, kSplitBins, K, c->d_part_cnt, c->d_part_base, nullptr, s)) !=
+                hipSuccess)
+                return err;
+            hipLaunchKernelGGL(k_sel_write, dim3(E * K), dim3(kSelThreads), 0, s, pk, peak_capacity, poff, roff,
+                               g.rz_max_candidates, K, c->d_part_base, c->d_cand);
+        } else {
+            hipLaunchKernelGGL(k_rz_select, dim3(E), dim3(256), 0, s,
+                               reinterpret_cast<const uint2 *>(peaks), peak_capacity, poff, roff,
+                               g.rz_max_candidates, c->d_cand);
+        }
         prof_end(c, s, &t);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }

@@ -187,11 +187,22 @@ def device_name(torch, device=0):
     return f"{p.name}/{arch}/{p.multi_processor_count}cu".replace("|", "/")
 
 
-def cached(spec, n_events, n_hits, device=0):
+def cached(spec, n_events, n_hits, device=0, path=CACHE):
     """The cached tuning of this workload shape on the current device, or
-    None when the cache has no entry for it."""
+    None when the cache has no entry for it.  When the device's name is not
+    in the cache (a profiler can report another marketing name), an entry
+    for the same ISA and workload shape is used if there is exactly one."""
     import torch
-    return lookup(workload_key(spec, n_events, n_hits, device_name(torch, device)))
+    dev = device_name(torch, device)
+    key = workload_key(spec, n_events, n_hits, dev)
+    t = lookup(key, path)
+    if t is not None:
+        return t
+    arch = dev.split("/")[-2] if dev.count("/") >= 2 else None
+    shape = key.split("|", 1)[1]
+    alike = [v for k, v in load_cache(path).items()
+             if k.split("|", 1)[1:] == [shape] and arch and k.split("|")[0].split("/")[-2:-1] == [arch]]
+    return dict(alike[0]["tuning"]) if len(alike) == 1 else None
 
 
 def tune_workload(name, n_events=None, reps=3, cache=CACHE, log=print):

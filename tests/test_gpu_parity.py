@@ -418,6 +418,28 @@ def test_rz_counter_overflow_goes_to_exact_path(H, bits, copies):
     assert grz["count"].max() >= 10 * copies
 
 
+def test_many_small_events_take_the_per_event_kernels(H):
+    """A batch of more than two events per compute unit: the layer sort and
+    the candidate selection run one workgroup per event (smaller batches
+    split each event over several workgroups); every event equals the
+    oracle, rz records with a candidate cap included."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    spec = small_spec(n_qpt=16, n_phi=64, rz_max_candidates=3)
+    evs = []
+    for e in range(2 * n_cu + 7):
+        rng = np.random.default_rng(5000 + e)
+        n = int(rng.integers(0, 60))
+        evs.append((rng.integers(0, 10, n).astype(np.uint8),
+                    rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
+                    rng.integers(-1_200_000, 1_200_000, n).astype(np.int32)))
+    batch = synth.concat_events(evs)
+    res = run_gpu(H, spec, batch)
+    tab = oracle.Tables(spec)
+    for e in range(batch.n_events):
+        check_event(H, tab, res, batch, e, rz=True)
+
+
 def test_rz_candidate_cap_selection(H):
     spec = small_spec(rz_max_candidates=37)
     batch = ragged_batch()
