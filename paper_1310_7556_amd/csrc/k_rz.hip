@@ -78,6 +78,21 @@ constexpr uint32_t kRzRedo = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// floor(a * b / 2^32) of the low 24 bits of a and b, one full-rate
+// instruction.  Written as an instruction of its own so that the compiler
+// keeps the product's high word and derives the counter address from it,
+// instead of recomputing the address from a second, low-word multiply.
+__device__ __forceinline__ uint32_t mulhi_u24(uint32_t a_uniform, uint32_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t r;
+    asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(r) : "s"(a_uniform), "v"(b));
+    return r;
+#else
+    return uint32_t((uint64_t(a_uniform & 0xFFFFFFu) * (b & 0xFFFFFFu)) >> 32);
+#endif
+}
+
 __device__ __forceinline__ uint64_t uni64(uint64_t v)
 {
     return uint64_t(uni(uint32_t(v))) | (uint64_t(uni(uint32_t(v >> 32))) << 32);
@@ -423,14 +438,17 @@ k_rz_vote_fast(RzParams P)
                 }
             }
         }
-        // 1b. exclusive prefix of window lengths across the layer lanes
+        // 1b. exclusive prefix of window lengths across the layer lanes:
+        // they are lanes 0..15 (L <= 15 here; the other lanes hold 0), one
+        // DPP row, scanned with row shifts by 1, 2, 4 and 8 lanes (a lane
+        // shifted in from before the row start reads 0)
         const uint32_t len = len1 + len2;
         uint32_t incl = len;
-        for (uint32_t d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, 64);
-            incl += lane >= d ? y : 0u;
-        }
-        const uint32_t T = uni(__shfl(incl, 63, 64));
+        incl += uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x111, 0xF, 0xF, false));   // row_shr:1
+        incl += uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x112, 0xF, 0xF, false));   // row_shr:2
+        incl += uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x114, 0xF, 0xF, false));   // row_shr:4
+        incl += uint32_t(__builtin_amdgcn_update_dpp(0, int(incl), 0x118, 0xF, 0xF, false));   // row_shr:8
+        const uint32_t T = uint32_t(__builtin_amdgcn_readlane(int(incl), 15));
         if (lane < 16) {
             lay[lane] = incl - len;
             lay[16 + lane] = len1;
@@ -568,7 +586,7 @@ k_rz_vote_fast(RzParams P)
                         const uint32_t u = zm[q] - zc[lq[q]];
                         if (MUL == 2) {
                             // both factors below 2^24: the 24-bit multiply-high
-                            b[q] = uint32_t((uint64_t(min(u, P.span24) & 0xFFFFFFu) * (P.bm & 0xFFFFFFu)) >> 32);
+                            b[q] = mulhi_u24(P.bm, min(u, P.span24));
                         } else {
                             uint32_t t = __umulhi(u, P.bm);
                             if (MUL == 1) t >>= P.bs;
@@ -578,8 +596,11 @@ k_rz_vote_fast(RzParams P)
                     }
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        // counter dword (b >> PSH) of this lane's column
-                        old[q] = atomicAdd(col + ((b[q] >> PSH) << 6), 1u << (sh[q] & 31u));
+                        // counter dword (b >> PSH) of this lane's column (a
+                        // bit-field extract keeps it one instruction plus a
+                        // shift-add)
+                        old[q] = atomicAdd(col + (__builtin_amdgcn_ubfe(b[q], PSH, 32 - PSH) << 6),
+                                           1u << (sh[q] & 31u));
                     }
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {

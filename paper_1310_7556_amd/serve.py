@@ -18,9 +18,44 @@ fake clock and backend; the GPU backend drives libhough.so.
 import collections
 import ctypes as C
 import dataclasses
+import os
 import time
 
 import numpy as np
+
+
+class Roctx:
+    """roctx ranges and marks for timelines of the serving loop (visible
+    under `rocprofv3 --marker-trace`); every call is a no-op when ROCm's
+    roctx library cannot be loaded."""
+
+    def __init__(self):
+        self.lib = None
+        root = os.environ.get("ROCM_PATH", "/opt/rocm")
+        for name in ("libroctx64.so", os.path.join(root, "lib", "libroctx64.so")):
+            try:
+                self.lib = C.CDLL(name)
+                break
+            except OSError:
+                continue
+        if self.lib is not None:
+            self.lib.roctxRangePushA.argtypes = [C.c_char_p]
+            self.lib.roctxMarkA.argtypes = [C.c_char_p]
+
+    def push(self, msg):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(msg.encode())
+
+    def pop(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
+
+    def mark(self, msg):
+        if self.lib is not None:
+            self.lib.roctxMarkA(msg.encode())
+
+
+ROCTX = Roctx()
 
 
 @dataclasses.dataclass
@@ -241,7 +276,6 @@ class GpuBackend:
         self.t_ref = self.clock.now()
 
     def launch(self, slot, batch):
-        H, torch = self.H, self.torch
         sl = self.slots[slot]
         n = len(batch)
         ev = np.array([r.event for r in batch], np.int64)
@@ -257,6 +291,17 @@ class GpuBackend:
             raise ValueError(f"micro-batch of {total} hits exceeds the slot capacity of "
                              f"{sl['layer'].numel()} hits")
         s = sl["stream"]
+        ROCTX.push(f"slot {slot}: micro-batch of {n} events, {total} hits")
+        try:
+            self._enqueue(sl, s, n, ih, total)
+        finally:
+            ROCTX.pop()
+        sl["batch"] = batch
+
+    def _enqueue(self, sl, s, n, ih, total):
+        """Enqueue one micro-batch's assembly, vote, peaks and rz on slot
+        stream s, then its completion event."""
+        H, torch = self.H, self.torch
         with torch.cuda.stream(s):
             sl["idx"].copy_(sl["idx_host"], non_blocking=True)
             if self.staged:
@@ -280,7 +325,6 @@ class GpuBackend:
                                              C.c_void_p(sl["poff"].data_ptr()), C.c_void_p(sl["rz"].data_ptr()),
                                              sl["rcap"], C.c_void_p(sl["roff"].data_ptr()), sp), ctx._h, "rz")
             sl["done"].record(s)
-        sl["batch"] = batch
 
     def next_completion(self):
         # completions are discovered by polling; report "now" while work is pending
@@ -291,6 +335,7 @@ class GpuBackend:
         for i, sl in enumerate(self.slots):
             if sl["batch"] is not None and sl["done"].query():
                 t_done = self.t_ref + self.ref.elapsed_time(sl["done"]) * 1e-3
+                ROCTX.mark(f"slot {i}: micro-batch of {len(sl['batch'])} events done")
                 if self.keep:
                     self._keep_results(sl)
                 sl["batch"] = None
