@@ -183,18 +183,30 @@ __device__ void rz_slow(const RzParams &P, uint64_t eb, const uint32_t *bo, uint
 
 // Wave argmax of (count desc, cot asc, z0 asc) over the lanes' bests, then
 // every lane stores the (uniform) record of candidate c.
+// Maximum of x over the wave's 64 lanes (all active), uniform: DPP swaps
+// within quads, rotates within rows of 16, then the last lane of each row
+// broadcast into the next rows.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x)
+{
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0xB1, 0xF, 0xF, false)));   // quad_perm 1,0,3,2
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x4E, 0xF, 0xF, false)));   // quad_perm 2,3,0,1
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x124, 0xF, 0xF, false)));  // row_ror:4
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x128, 0xF, 0xF, false)));  // row_ror:8
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x142, 0xA, 0xF, false)));  // row_bcast:15
+    x = max(x, uint32_t(__builtin_amdgcn_update_dpp(int(x), int(x), 0x143, 0xC, 0xF, false)));  // row_bcast:31
+    return uint32_t(__builtin_amdgcn_readlane(int(x), 63));
+}
+
 __device__ __forceinline__ void rz_finish(const RzParams &P, uint64_t c, uint32_t pk, uint32_t nm,
                                           uint32_t best_c, uint32_t best_j, uint32_t best_b)
 {
-    uint64_t key = (uint64_t(best_c) << 32) | (uint64_t(0xFFFFu - (best_j & 0xFFFFu)) << 16) |
-                   (0xFFFFu - (best_b & 0xFFFFu));
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(key, off, 64);
-        key = o > key ? o : key;
-    }
-    const uint32_t cnt = uint32_t(key >> 32);
-    const uint32_t jj = 0xFFFFu - uint32_t((key >> 16) & 0xFFFFu);
-    const uint32_t bb = 0xFFFFu - uint32_t(key & 0xFFFFu);
+    // the largest count, then among the lanes holding it the smallest cot
+    // bin and then the smallest z0 bin (as one 32-bit key)
+    const uint32_t cnt = wave_max_u32(best_c);
+    const uint32_t key = best_c == cnt ? ((0xFFFFu - (best_j & 0xFFFFu)) << 16) | (0xFFFFu - (best_b & 0xFFFFu)) : 0u;
+    const uint32_t kmax = wave_max_u32(key);
+    const uint32_t jj = 0xFFFFu - (kmax >> 16);
+    const uint32_t bb = 0xFFFFu - (kmax & 0xFFFFu);
     uint2 a, b;
     a.x = pk;
     a.y = (cnt ? jj : 0u) | ((cnt ? bb : 0u) << 16);
