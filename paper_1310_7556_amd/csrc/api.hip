@@ -87,6 +87,9 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.vote_algo == 5 && !c->d_rk_info) return false;
     if (t.vote_items > 2) return false;
     if (t.peak_algo > 2) return false;
+    if (t.rz_member_cap && (t.rz_member_cap < 256 || t.rz_member_cap > 4096 ||
+                            (t.rz_member_cap & (t.rz_member_cap - 1))))
+        return false;
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 4 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16)
         return false;

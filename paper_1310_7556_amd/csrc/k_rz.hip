@@ -66,6 +66,7 @@ struct RzParams {
     int lds_ok;                   // general kernel: the uint16 histogram fits in LDS
     uint32_t bm, bs;              // fast path: bin = mulhi(u, bm) >> bs
     uint32_t span24;              // MUL == 2: span (< 2^24, with bm < 2^24 and bs == 0)
+    uint32_t redo_lds;            // k_rz_redo has LDS for kRedoMembers members and an n_z0 histogram
     uint32_t hw;                  // fast path: counter dwords per lane
     uint32_t mcap;                // fast path: member list capacity
 };
@@ -644,10 +645,13 @@ k_rz_vote_fast(RzParams P)
                 // cot bins are counted (nothing to clear after an empty pass)
                 if (nq) {
                     __syncthreads();
-                    uint4 *h4 = reinterpret_cast<uint4 *>(hist);
-                    const uint32_t n4 = P.hw * 16;
-#pragma unroll 4
-                    for (uint32_t i = lane; i < n4; i += 64) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+                    // full rounds of 64 16-byte stores at fixed offsets from
+                    // one address, then the partial last round
+                    uint4 *h4 = reinterpret_cast<uint4 *>(hist) + lane;
+                    const uint32_t n4 = P.hw * 16, full = n4 >> 6;
+#pragma unroll 8
+                    for (uint32_t k = 0; k < full; ++k) h4[k * 64] = make_uint4(0u, 0u, 0u, 0u);
+                    if (lane < (n4 & 63u)) h4[full * 64] = make_uint4(0u, 0u, 0u, 0u);
                 }
                 __syncthreads();
                 if (jv && bc > best_c) { best_c = bc; best_j = j; best_b = bb; }
@@ -671,12 +675,59 @@ k_rz_vote_fast(RzParams P)
     }
 }
 
-// The exact slow path for the records k_rz_vote_fast marked (count ==
-// kRzRedo): one wave per 64 records, each marked candidate recomputed with
-// the global-memory histogram of the wave's workgroup (grid-stride over
-// record groups; at most rz_blocks workgroups, one histogram each).
+// The exact path for the records k_rz_vote_fast marked (count == kRzRedo):
+// one wave per 64 records, each marked candidate recomputed exactly
+// (grid-stride over record groups; at most rz_blocks workgroups).  With
+// redo_lds and at most kRedoMembers members, the members are gathered into
+// LDS once and counted per cot bin in an LDS histogram of the n_z0 bins,
+// every lane taking every 64th member; otherwise rz_slow with the global
+// histogram of the wave's workgroup.
+constexpr uint32_t kRedoMembers = 8192;
+
+__device__ void rz_exact_lds(const RzParams &P, const RzCand &r, int32_t *mz, uint8_t *ml, uint32_t *hist,
+                             uint32_t lane, uint32_t &best_c, uint32_t &best_j, uint32_t &best_b)
+{
+    // members in walk order; member i is written by lane i % 64
+    uint32_t seen = 0;
+    for_members(P, r.eb, r.bo, r.k, r.p, r.mask, [&](uint32_t h, uint32_t l) {
+        if ((seen & 63u) == lane) {
+            mz[seen] = P.z[r.eb + h];
+            ml[seen] = uint8_t(l);
+        }
+        ++seen;
+    });
+    const uint32_t nm = uni(seen);
+    best_c = 0;
+    best_j = 0;
+    best_b = 0;
+    for (uint32_t j = 0; j < P.n_cot; ++j) {
+        for (uint32_t i = lane; i < P.n_z0; i += 64) hist[i] = 0;
+        __syncthreads();
+        for (uint32_t m = lane; m < nm; m += 64) {
+            const int64_t zl = int64_t(P.Z[(size_t(r.k) * P.n_layers + ml[m]) * P.n_cot + j]) + P.z0_lo;
+            const int32_t b = z0_bin(P, mz[m], zl);
+            if (b >= 0) atomicAdd(&hist[b], 1u);
+        }
+        __syncthreads();
+        // the largest count of the cot bin, then its smallest z0 bin
+        uint32_t cnt = 0, bin = 0;
+        for (uint32_t i = lane; i < P.n_z0; i += 64) {
+            const uint32_t v = hist[i];
+            if (v > cnt) { cnt = v; bin = i; }
+        }
+        const uint32_t cmax = wave_max_u32(cnt);
+        const uint32_t bkey = wave_max_u32(cmax != 0 && cnt == cmax ? 0xFFFFu - bin : 0u);
+        if (cmax > best_c) { best_c = cmax; best_j = j; best_b = 0xFFFFu - bkey; }
+        __syncthreads();                              // histogram read before the next clear
+    }
+}
+
 __global__ void __launch_bounds__(64) k_rz_redo(RzParams P)
 {
+    HOUGH_DYNAMIC_LDS(uint32_t, rl);                  // with redo_lds: z [kRedoMembers], layers, histogram
+    int32_t *mz = reinterpret_cast<int32_t *>(rl);
+    uint8_t *ml = reinterpret_cast<uint8_t *>(rl + kRedoMembers);
+    uint32_t *hist = rl + kRedoMembers + kRedoMembers / 4;
     const uint32_t lane = threadIdx.x;
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
     uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
@@ -691,7 +742,10 @@ __global__ void __launch_bounds__(64) k_rz_redo(RzParams P)
             const RzCand r = rz_decode(P, cc);
             const uint32_t nm = uni(P.out4[2 * cc + 1].y);     // the fast kernel's member count
             uint32_t best_c = 0, best_j = 0, best_b = 0;
-            rz_slow(P, r.eb, r.bo, r.k, r.p, r.mask, g, lane, best_c, best_j, best_b);
+            if (P.redo_lds && nm <= kRedoMembers)
+                rz_exact_lds(P, r, mz, ml, hist, lane, best_c, best_j, best_b);
+            else
+                rz_slow(P, r.eb, r.bo, r.k, r.p, r.mask, g, lane, best_c, best_j, best_b);
             if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
             rz_finish(P, cc, r.pk, nm, best_c, best_j, best_b);
         }
@@ -973,13 +1027,15 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     // counter dwords per lane: bins 0 .. n_z0 - 1 plus the trash bin n_z0
     const uint32_t hw = g.n_z0 / (32 / bits) + 1;
     // member lists: 112 with 4-bit counters (16 waves of counters and two
-    // lists fit 160 KB); otherwise as many as fit the LDS budget, up to 4096: a
-    // candidate with more members takes the slow path, which is far slower
-    // (it walks every hit of the cell's windows per cot bin), so dense
-    // events need the long list more than occupancy
+    // lists fit 160 KB); otherwise 2048 (tunable), reduced until it fits the
+    // LDS budget: a candidate with more members goes to k_rz_redo, whose
+    // exact path is far slower per candidate, so dense events need a list
+    // that holds their cells; a 4096-member list only costs occupancy
+    // (16-event c5 micro-batches: rz 1.40 ms with 4096, 0.87 ms with 2048,
+    // and 0.87 ms plus 40 ms of exact path with 1024)
     uint32_t mcap = bits == 4 ? 112 : 256;
     if (bits != 4) {
-        mcap = 4096;
+        mcap = c->tun.rz_member_cap ? c->tun.rz_member_cap : 2048;
         while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;
     }
     const size_t fast_lds = size_t(rz_fast_lds_dwords(hw, mcap)) * 4;
@@ -1002,8 +1058,11 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         // candidates the fast kernel marked; the grid covers every record
         // group and uses at most the slow path's histograms
         const uint64_t groups = std::max<uint64_t>(1, (rz_records_bound(c, h, peak_capacity, capacity) + 63) / 64);
+        const size_t redo_lds = (size_t(kRedoMembers) * 5 + size_t(g.n_z0) * 4 + 15) & ~size_t(15);
+        P.redo_lds = redo_lds <= c->max_lds ? 1u : 0u;
         prof_begin(c, "rz_redo", s, &t);
-        hipLaunchKernelGGL(k_rz_redo, dim3(uint32_t(std::min<uint64_t>(groups, rz_blocks_max(c)))), dim3(64), 0, s, P);
+        hipLaunchKernelGGL(k_rz_redo, dim3(uint32_t(std::min<uint64_t>(groups, rz_blocks_max(c)))), dim3(64),
+                           P.redo_lds ? redo_lds : 0, s, P);
         prof_end(c, s, &t);
         return hipGetLastError();
     }

@@ -131,6 +131,77 @@ k_vote_bounds(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ ph
     }
 }
 
+// Split form of k_vote_bounds for batches of few events: the table is first
+// filled with {min, max} = {0xFFFFFFFF, 0}; each of an event's K parts (a
+// workgroup over a K-th of its hits) finds its own minima and maxima in LDS
+// and merges the non-empty ones into the table with global atomic min/max;
+// then one workgroup per (event, layer) turns the row's {min, max} into
+// {lo, span} exactly as k_vote_bounds does.
+__global__ void k_bounds_init(uint2 *__restrict__ tab, uint64_t n)
+{
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        tab[i] = make_uint2(0xFFFFFFFFu, 0u);
+}
+
+__global__ void __launch_bounds__(256)
+k_bounds_part(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
+              const uint64_t *__restrict__ offs, uint64_t n_hits, uint32_t n_layers, uint32_t nphi, uint32_t shift,
+              uint32_t group_layers, uint32_t K, uint2 *__restrict__ tab)
+{
+    HOUGH_DYNAMIC_LDS(uint32_t, lds);                // bmin[gl][nphi], bmax[gl][nphi]
+    const uint32_t e = blockIdx.x / K, k = blockIdx.x % K, t = threadIdx.x, nt = blockDim.x;
+    const uint64_t b0 = min(offs[e], n_hits);
+    uint64_t end0 = min(offs[e + 1], n_hits);
+    if (end0 < b0) end0 = b0;
+    const uint64_t len = end0 - b0;
+    const uint64_t b = b0 + len * k / K, end = b0 + len * (k + 1) / K;
+    for (uint32_t l0 = 0; l0 < n_layers; l0 += group_layers) {
+        const uint32_t gl = min(group_layers, n_layers - l0);
+        uint32_t *bmin = lds, *bmax = lds + gl * nphi;
+        for (uint32_t i = t; i < gl * nphi; i += nt) {
+            bmin[i] = 0xFFFFFFFFu;
+            bmax[i] = 0u;
+        }
+        __syncthreads();
+        for (uint64_t i = b + t; i < end; i += nt) {
+            const uint32_t l = layer[i];
+            if (l >= l0 && l < l0 + gl) {
+                const uint32_t ph = phi[i];
+                const uint32_t bi = (l - l0) * nphi + (ph >> shift);
+                atomicMin(&bmin[bi], ph);
+                atomicMax(&bmax[bi], ph);
+            }
+        }
+        __syncthreads();
+        uint2 *out = tab + (size_t(e) * n_layers + l0) * nphi;
+        for (uint32_t i = t; i < gl * nphi; i += nt) {
+            if (bmin[i] <= bmax[i]) {
+                atomicMin(&out[i].x, bmin[i]);
+                atomicMax(&out[i].y, bmax[i]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_bounds_final(uint32_t nphi, uint32_t shift, uint2 *__restrict__ tab)
+{
+    HOUGH_DYNAMIC_LDS(uint2, row);                   // [nphi] {min, max}
+    const uint32_t t = threadIdx.x, nt = blockDim.x;
+    const uint32_t wmask = (1u << shift) - 1u;
+    uint2 *r = tab + size_t(blockIdx.x) * nphi;      // one (event, layer) row
+    for (uint32_t j = t; j < nphi; j += nt) row[j] = r[j];
+    __syncthreads();
+    for (uint32_t j = t; j < nphi; j += nt) {
+        const uint2 a = row[j], n = row[(j + 1) & (nphi - 1)];
+        const bool ne = a.x <= a.y, ne1 = n.x <= n.y;
+        const uint32_t lo = ne ? (a.y & wmask) + 1u : 0u;        // may equal W: never empty
+        const uint32_t hi = ne1 ? (n.x & wmask) : wmask;
+        r[j] = hi >= lo ? make_uint2(lo, hi - lo) : make_uint2(0xFFFFFFFFu, 0u);
+    }
+}
+
 // One workgroup of nt threads (a multiple of 64) per item.  Work unit = (tile,
 // group of CPW 64-cell column chunks); waves take units round-robin.  For
 // each layer, from the highest down, a lane walks the R rows of the tile
@@ -286,9 +357,28 @@ hipError_t launch_vote_bounds(hough_ctx *c, const hough_hits *h, hipStream_t s)
     const int vec = (reinterpret_cast<uintptr_t>(h->layer) & 3) == 0 && (reinterpret_cast<uintptr_t>(h->phi) & 15) == 0;
     KernelTimer t;
     prof_begin(c, "vote_bounds", s, &t);
-    hipLaunchKernelGGL(k_vote_bounds, dim3(E), dim3(1024), size_t(group) * c->spec.n_phi * 8, s, h->layer, h->phi,
-                       h->event_offsets, h->n_hits, c->spec.n_layers, c->spec.n_phi, c->log2_phi, c->shift, group,
-                       vec, c->d_dir_tab);
+    // split only events with many hits per table entry (at least 16): the
+    // split form costs two more launches, and each part initialises and
+    // merges its event's whole (layer, bucket) table (the 198k-hit displaced
+    // event: 42 us in one workgroup, 22 us in 64 parts; the 20k-hit event on
+    // 10 x 1024 entries: 13 us in one, 18 us in 64 parts)
+    const uint64_t entries = uint64_t(c->spec.n_layers) * c->spec.n_phi;
+    const uint64_t per_event = E ? h->n_hits / E : 0;
+    const uint32_t K = per_event >= 16 * entries ? split_parts(c, E) : 0;
+    if (K >= 2) {
+        const uint64_t n = uint64_t(E) * entries;
+        hipLaunchKernelGGL(k_bounds_init, dim3(uint32_t(std::min<uint64_t>((n + 255) / 256, 4096))), dim3(256), 0, s,
+                           c->d_dir_tab, n);
+        hipLaunchKernelGGL(k_bounds_part, dim3(E * K), dim3(256), size_t(group) * c->spec.n_phi * 8, s, h->layer,
+                           h->phi, h->event_offsets, h->n_hits, c->spec.n_layers, c->spec.n_phi, c->shift, group, K,
+                           c->d_dir_tab);
+        hipLaunchKernelGGL(k_bounds_final, dim3(E * c->spec.n_layers), dim3(256), size_t(c->spec.n_phi) * 8, s,
+                           c->spec.n_phi, c->shift, c->d_dir_tab);
+    } else {
+        hipLaunchKernelGGL(k_vote_bounds, dim3(E), dim3(1024), size_t(group) * c->spec.n_phi * 8, s, h->layer,
+                           h->phi, h->event_offsets, h->n_hits, c->spec.n_layers, c->spec.n_phi, c->log2_phi,
+                           c->shift, group, vec, c->d_dir_tab);
+    }
     prof_end(c, s, &t);
     return hipGetLastError();
 }

@@ -302,6 +302,30 @@ def test_unaligned_accumulator_peaks_take_the_tile_form(H):
         np.testing.assert_array_equal(H.peaks_numpy(pk, poff, e), opk.astype(H.PEAK_DTYPE), err_msg=f"event {e}")
 
 
+@pytest.mark.parametrize("tuning,n_phi,sizes", [
+    (dict(vote_algo=4), 64, [40000, 0, 33333, 25000]),
+    (dict(vote_algo=5, vote_items=2), 256, [120000, 0, 90000, 60000]),
+])
+def test_bucket_bounds_split_over_parts_of_dense_events(H, tuning, n_phi, sizes):
+    """Few dense events (at least 16 hits per (layer, bucket) entry on
+    average): the bucket bounds are found by several workgroups per event and
+    merged with global atomic min/max; accumulators and peaks equal the
+    oracle's."""
+    spec = small_spec(n_phi=n_phi, n_qpt=24, n_z0=0, n_cot=0)
+    assert sum(sizes) // len(sizes) >= 16 * spec["n_layers"] * n_phi
+    evs = []
+    for e, n in enumerate(sizes):
+        rng = np.random.default_rng(900 + e)
+        evs.append((rng.integers(0, 10, n).astype(np.uint8),
+                    rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
+                    np.zeros(n, np.int32)))
+    batch = synth.concat_events(evs)
+    res = run_gpu(H, spec, batch, tuning=tuning, rz=False)
+    tab = oracle.Tables(spec)
+    for e in range(batch.n_events):
+        check_event(H, tab, res, batch, e)
+
+
 def test_unaligned_hit_arrays_and_accumulator(H):
     """Hit arrays that start one element past an aligned address and an
     accumulator that is 4- but not 8-byte aligned take the scalar load paths
@@ -378,8 +402,12 @@ def test_peak_and_rz_capacity_overflow(H):
     # up to about 3000 members per cell: within the 8-bit form's 4096-member
     # list (counts past 255 are caught as overflows and redone exactly)
     (dict(rz_counter_bits=8), dict(n_phi=4, n_qpt=8, n_cot=70)),
-    # up to about 6000 members per cell: past every member list, so the slow path
+    # up to about 6000 members per cell: past every member list, so the exact
+    # path with the members in LDS
     (dict(rz_counter_bits=16), dict(n_phi=2, n_qpt=4, n_cot=9)),
+    # shorter member lists than the cells need: the exact path for many
+    # candidates
+    (dict(rz_counter_bits=8, rz_member_cap=256), dict(n_phi=16, n_qpt=8, n_cot=40)),
     (None, dict(z0_lo_um=-2147483000, z0_hi_um=2147483000, n_z0=64)),  # general kernel
     (None, dict(cot_lo=1.2, cot_hi=-1.2)),          # Z decreasing in the cot bin
     (None, dict(n_cot=100)),                        # a last pass of 36 cot bins
@@ -391,6 +419,21 @@ def test_rz_kernel_variants(H, tuning, kw):
     tab = oracle.Tables(spec)
     for e in range(batch.n_events):
         check_event(H, tab, res, batch, e, rz=True)
+
+
+def test_rz_exact_path_past_the_lds_member_list(H):
+    """A cell with more members than the exact path's LDS list (8192): the
+    global-histogram path, against the oracle."""
+    spec = small_spec(n_phi=2, n_qpt=4, n_cot=7, n_z0=32)
+    rng = np.random.default_rng(77)
+    n = 20000
+    batch = synth.concat_events([(rng.integers(0, 10, n).astype(np.uint8),
+                                  rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
+                                  rng.integers(-1_200_000, 1_200_000, n).astype(np.int32))])
+    res = run_gpu(H, spec, batch, tuning=dict(rz_counter_bits=16))
+    tab = oracle.Tables(spec)
+    check_event(H, tab, res, batch, 0, rz=True)
+    assert H.rz_numpy(res["rz"], res["roff"], 0)["n_members"].max() > 8192
 
 
 @pytest.mark.parametrize("bits,copies", [(4, 3), (8, 3), (16, 3), (8, 26)])
@@ -418,14 +461,16 @@ def test_rz_counter_overflow_goes_to_exact_path(H, bits, copies):
     assert grz["count"].max() >= 10 * copies
 
 
-def test_many_small_events_take_the_per_event_kernels(H):
-    """A batch of more than two events per compute unit: the layer sort and
-    the candidate selection run one workgroup per event (smaller batches
-    split each event over several workgroups); every event equals the
-    oracle, rz records with a candidate cap included."""
+@pytest.mark.parametrize("tuning", [None, dict(vote_algo=4), dict(vote_algo=5, vote_items=2)])
+def test_many_small_events_take_the_per_event_kernels(H, tuning):
+    """A batch of more than two events per compute unit: the layer sort,
+    the bucket bounds (direct form and the rank form's tile mode) and the
+    candidate selection run one workgroup per event (smaller batches split
+    each event over several workgroups); every event equals the oracle, rz
+    records with a candidate cap included."""
     import torch
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
-    spec = small_spec(n_qpt=16, n_phi=64, rz_max_candidates=3)
+    spec = small_spec(n_qpt=16, n_phi=256, rz_max_candidates=3)
     evs = []
     for e in range(2 * n_cu + 7):
         rng = np.random.default_rng(5000 + e)
@@ -434,7 +479,7 @@ def test_many_small_events_take_the_per_event_kernels(H):
                     rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
                     rng.integers(-1_200_000, 1_200_000, n).astype(np.int32)))
     batch = synth.concat_events(evs)
-    res = run_gpu(H, spec, batch)
+    res = run_gpu(H, spec, batch, tuning=tuning)
     tab = oracle.Tables(spec)
     for e in range(batch.n_events):
         check_event(H, tab, res, batch, e, rz=True)
