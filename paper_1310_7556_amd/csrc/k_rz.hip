@@ -763,6 +763,44 @@ __global__ void k_rz_counts(const uint64_t *__restrict__ poff, uint64_t peak_cap
     counts[e] = uint32_t(cap ? min(n, uint64_t(cap)) : n);
 }
 
+// For batches of up to kRzOffsetsMaxEvents events, in one workgroup: the
+// candidate count of every event (as k_rz_counts), their exclusive prefix
+// into roff[0..E] and the reset of the work counter -- one launch where the
+// general path takes three.
+constexpr uint32_t kRzOffsetsMaxEvents = 1024 * 8;
+
+__global__ void __launch_bounds__(1024)
+k_rz_offsets(const uint64_t *__restrict__ poff, uint64_t peak_capacity, uint32_t n_events, uint32_t cap,
+             uint64_t *__restrict__ roff, uint32_t *__restrict__ counter)
+{
+    __shared__ uint64_t part[1024];
+    const uint32_t t = threadIdx.x, nt = blockDim.x;
+    auto count = [&](uint32_t e) {
+        const uint64_t lo = min(poff[e], peak_capacity), hi = min(max(poff[e + 1], poff[e]), peak_capacity);
+        const uint64_t n = hi - lo;
+        return cap ? min(n, uint64_t(cap)) : n;
+    };
+    const uint32_t per = (n_events + nt - 1) / nt;
+    const uint32_t b = min(t * per, n_events), end = min(b + per, n_events);
+    uint64_t s = 0;
+    for (uint32_t e = b; e < end; ++e) s += count(e);
+    part[t] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < nt; off <<= 1) {
+        const uint64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint64_t run = t ? part[t - 1] : 0;
+    for (uint32_t e = b; e < end; ++e) {
+        roff[e] = run;
+        run += count(e);
+    }
+    if (t == nt - 1) roff[n_events] = part[nt - 1];
+    if (t == 0) *counter = 0;
+}
+
 // Candidate selection with a cap: the first cap peaks of the event ordered
 // by (popcount desc, cell asc), i.e. a stable partition by popcount.  One
 // workgroup of 256 threads per event.
@@ -953,12 +991,17 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     if ((err = launch_bucket_layers(c, h, true, s)) != hipSuccess) return err;
     if ((err = launch_bucket_phi(c, h, s)) != hipSuccess) return err;
     KernelTimer t;
+    const bool fused = E <= kRzOffsetsMaxEvents;
     prof_begin(c, "rz_counts", s, &t);
-    hipLaunchKernelGGL(k_rz_counts, dim3((E + 255) / 256), dim3(256), 0, s, poff, peak_capacity, E,
-                       g.rz_max_candidates, c->d_cand_counts);
+    if (fused)
+        hipLaunchKernelGGL(k_rz_offsets, dim3(1), dim3(1024), 0, s, poff, peak_capacity, E, g.rz_max_candidates,
+                           roff, c->d_counters + 1);
+    else
+        hipLaunchKernelGGL(k_rz_counts, dim3((E + 255) / 256), dim3(256), 0, s, poff, peak_capacity, E,
+                           g.rz_max_candidates, c->d_cand_counts);
     prof_end(c, s, &t);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    if ((err = launch_scan_counts(c, c->d_cand_counts, E, c->d_tile_off, 1, roff, s)) != hipSuccess)
+    if (!fused && (err = launch_scan_counts(c, c->d_cand_counts, E, c->d_tile_off, 1, roff, s)) != hipSuccess)
         return err;
     if (g.rz_max_candidates) {
         prof_begin(c, "rz_select", s, &t);
@@ -979,7 +1022,7 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         prof_end(c, s, &t);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    if ((err = launch_fill_u32(c, c->d_counters + 1, 0, 1, s)) != hipSuccess) return err;
+    if (!fused && (err = launch_fill_u32(c, c->d_counters + 1, 0, 1, s)) != hipSuccess) return err;
 
     RzParams P;
     P.phi = c->d_phi_b;

@@ -485,6 +485,33 @@ def test_many_small_events_take_the_per_event_kernels(H, tuning):
         check_event(H, tab, res, batch, e, rz=True)
 
 
+def test_rz_offsets_of_a_batch_past_the_one_workgroup_scan(H):
+    """More events (8,300) than the fused one-workgroup candidate-offset
+    kernel takes: the count, scan and counter-reset launches; every event's
+    rz records equal the oracle's."""
+    spec = small_spec(n_qpt=4, n_phi=8, n_cot=16, n_z0=16, rz_max_candidates=2)
+    evs = []
+    rng = np.random.default_rng(31)
+    for e in range(8300):
+        n = int(rng.integers(0, 4))
+        evs.append((rng.integers(0, 10, n).astype(np.uint8),
+                    rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
+                    rng.integers(-1_200_000, 1_200_000, n).astype(np.int32)))
+    batch = synth.concat_events(evs)
+    res = run_gpu(H, spec, batch)
+    tab = oracle.Tables(spec)
+    roff = H.offsets_numpy(res["roff"]).astype(np.int64)
+    want = [0]
+    for e in range(batch.n_events):
+        ev = batch.event(e)
+        _, opk, orz = oracle.run_event(tab, ev.layer, ev.phi, ev.z)
+        want.append(want[-1] + len(orz))
+        if e % 97 == 0:
+            np.testing.assert_array_equal(H.rz_numpy(res["rz"], res["roff"], e), orz.astype(H.RZ_DTYPE),
+                                          err_msg=f"rz of event {e}")
+    np.testing.assert_array_equal(roff, np.array(want, np.int64))
+
+
 def test_rz_candidate_cap_selection(H):
     spec = small_spec(rz_max_candidates=37)
     batch = ragged_batch()
