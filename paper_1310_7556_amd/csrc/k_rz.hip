@@ -676,13 +676,14 @@ k_rz_vote_fast(RzParams P)
 }
 
 // The exact path for the records k_rz_vote_fast marked (count == kRzRedo):
-// one wave per 64 records, each marked candidate recomputed exactly
+// one wave per group of 8 records, each marked candidate recomputed exactly
 // (grid-stride over record groups; at most rz_blocks workgroups).  With
 // redo_lds and at most kRedoMembers members, the members are gathered into
 // LDS once and counted per cot bin in an LDS histogram of the n_z0 bins,
 // every lane taking every 64th member; otherwise rz_slow with the global
 // histogram of the wave's workgroup.
 constexpr uint32_t kRedoMembers = 8192;
+constexpr uint32_t kRedoGroup = 8;
 
 __device__ void rz_exact_lds(const RzParams &P, const RzCand &r, int32_t *mz, uint8_t *ml, uint32_t *hist,
                              uint32_t lane, uint32_t &best_c, uint32_t &best_j, uint32_t &best_b)
@@ -731,9 +732,11 @@ __global__ void __launch_bounds__(64) k_rz_redo(RzParams P)
     const uint32_t lane = threadIdx.x;
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
     uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
-    for (uint64_t c0 = uint64_t(blockIdx.x) * 64; c0 < total; c0 += uint64_t(gridDim.x) * 64) {
+    // groups of kRedoGroup records, so that marked candidates that are
+    // neighbours in the record list (a dense event's) spread over many waves
+    for (uint64_t c0 = uint64_t(blockIdx.x) * kRedoGroup; c0 < total; c0 += uint64_t(gridDim.x) * kRedoGroup) {
         const uint64_t c = c0 + lane;
-        const bool redo = c < total && P.out4[2 * c + 1].x == kRzRedo;
+        const bool redo = lane < kRedoGroup && c < total && P.out4[2 * c + 1].x == kRzRedo;
         uint64_t bal = __ballot(redo);
         while (bal) {
             const uint32_t b = __ffsll(static_cast<unsigned long long>(bal)) - 1;
@@ -1077,7 +1080,7 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     // (16-event c5 micro-batches: rz 1.40 ms with 4096, 0.87 ms with 2048,
     // and 0.87 ms plus 40 ms of exact path with 1024)
     uint32_t mcap = bits == 4 ? 112 : 256;
-    if (bits != 4) {
+    if (bits != 4 || c->tun.rz_member_cap) {
         mcap = c->tun.rz_member_cap ? c->tun.rz_member_cap : 2048;
         while (mcap > 256 && size_t(rz_fast_lds_dwords(hw, mcap)) * 4 > c->max_lds) mcap >>= 1;
     }
@@ -1100,7 +1103,8 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         if ((err = hipGetLastError()) != hipSuccess) return err;
         // candidates the fast kernel marked; the grid covers every record
         // group and uses at most the slow path's histograms
-        const uint64_t groups = std::max<uint64_t>(1, (rz_records_bound(c, h, peak_capacity, capacity) + 63) / 64);
+        const uint64_t groups =
+            std::max<uint64_t>(1, (rz_records_bound(c, h, peak_capacity, capacity) + kRedoGroup - 1) / kRedoGroup);
         const size_t redo_lds = (size_t(kRedoMembers) * 5 + size_t(g.n_z0) * 4 + 15) & ~size_t(15);
         P.redo_lds = redo_lds <= c->max_lds ? 1u : 0u;
         prof_begin(c, "rz_redo", s, &t);
