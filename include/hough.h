@@ -182,9 +182,12 @@ typedef struct {
     uint32_t peak_algo;             /* peak search: 0 = default (2 where usable, else 1), 1 = tiles staged
                                        in LDS, 2 = row window in registers (n_d0 == 1, n_phi 256, 512 or
                                        1024, accumulator 16-byte aligned, 8 for n_phi 256) */
-    uint32_t rz_member_cap;         /* rz with 8- or 16-bit counters: members a candidate may have on the
-                                       fast path (a power of two, 256 to 4096; more go to the exact path);
-                                       0 = as many as fit the LDS budget */
+    uint32_t rz_member_cap;         /* rz: members a candidate may have on the fast path (a power of two,
+                                       256 to 4096; more go to the exact path); 0 = 112 with 4-bit
+                                       counters, else as many as fit the LDS budget (at most 2048) */
+    uint32_t rz_redo_list;          /* rz: capacity of the list of candidates left to the exact path
+                                       (1 to 65536, 0 = 65536); when more are left, the exact-path kernel
+                                       scans every record for them instead */
 } hough_tuning;
 
 /* ---- context --------------------------------------------------------- */

@@ -48,7 +48,7 @@ void free_all(hough_ctx *c)
 {
     void *ptrs[] = {c->d_O, c->d_V, c->d_Z, c->d_Zl, c->d_rk_info, c->d_rk_sorted, c->d_phi_a, c->d_z_a, c->d_phi_b, c->d_z_b,
                     c->d_layer_off, c->d_bucket_off, c->d_order, c->d_counters, c->d_tile_counts,
-                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_gap_info, c->d_gap_list,
+                    c->d_tile_off, c->d_cand, c->d_cand_counts, c->d_rz_hist, c->d_redo_list, c->d_gap_info, c->d_gap_list,
                     c->d_scan_part, c->d_scan_off, c->d_dir_tab, c->d_cl_rank, c->d_cl_part,
                     c->d_cl_part_off, c->d_part_cnt, c->d_part_base};
     for (void *p : ptrs)
@@ -90,6 +90,7 @@ bool tuning_ok(const hough_ctx *c, const hough_tuning &t)
     if (t.rz_member_cap && (t.rz_member_cap < 256 || t.rz_member_cap > 4096 ||
                             (t.rz_member_cap & (t.rz_member_cap - 1))))
         return false;
+    if (t.rz_redo_list > hough::kRedoListCap) return false;
     if (t.rz_slow_path > 1) return false;
     if (t.rz_counter_bits != 0 && t.rz_counter_bits != 4 && t.rz_counter_bits != 8 && t.rz_counter_bits != 16)
         return false;
@@ -255,9 +256,10 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
               dev_alloc(&c->d_phi_b, buckets ? H : 0) && dev_alloc(&c->d_z_b, rz ? H : 0) &&
               dev_alloc(&c->d_layer_off, size_t(E) * (L + 1)) &&
               dev_alloc(&c->d_bucket_off, size_t(E) * L * nb) && dev_alloc(&c->d_order, E) &&
-              dev_alloc(&c->d_counters, 64) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&
+              dev_alloc(&c->d_counters, kCounterDwords) && dev_alloc(&c->d_tile_counts, c->n_peak_tiles) &&
               dev_alloc(&c->d_tile_off, c->n_peak_tiles + 1) && dev_alloc(&c->d_cand, ncand) &&
               dev_alloc(&c->d_cand_counts, E) && dev_alloc(&c->d_rz_hist, rzh) &&
+              dev_alloc(&c->d_redo_list, rz ? kRedoListCap : 0) &&
               dev_alloc(&c->d_part_cnt, c->max_parts * kSplitBins) &&
               dev_alloc(&c->d_part_base, c->max_parts * kSplitBins) &&
               dev_alloc(&c->d_gap_info, size_t(E) * L) && dev_alloc(&c->d_gap_list, H) &&
@@ -283,7 +285,7 @@ int hough_create(const hough_grid_spec *spec, const hough_limits *limits, int de
         err = hipMemcpy(c->d_rk_info, rk_info.data(), rk_info.size() * 4, hipMemcpyHostToDevice);
     if (err == hipSuccess && !rk_sorted.empty())
         err = hipMemcpy(c->d_rk_sorted, rk_sorted.data(), rk_sorted.size() * 4, hipMemcpyHostToDevice);
-    if (err == hipSuccess) err = hipMemset(c->d_counters, 0, 64 * 4);
+    if (err == hipSuccess) err = hipMemset(c->d_counters, 0, kCounterDwords * 4);
     if (err == hipSuccess) err = hipDeviceSynchronize();
     // the static scratch of hough_peaks_noalloc: its address on this device,
     // looked up once per device (a failure is reported by that call)

@@ -79,7 +79,7 @@ struct hough_ctx {
     uint32_t *d_layer_off = nullptr; // [max_events][L + 1] relative to the event start
     uint32_t *d_bucket_off = nullptr;// [max_events][L][NB + 1]
     uint32_t *d_order = nullptr;     // [max_events] events, longest first
-    uint32_t *d_counters = nullptr;  // [64] work-queue counters
+    uint32_t *d_counters = nullptr;  // [kCounterDwords] work-queue counters
     uint32_t *d_tile_counts = nullptr; // [max peak tiles]
     uint64_t *d_tile_off = nullptr;    // [max peak tiles + 1]
     uint32_t *d_cand = nullptr;        // [max_events * rz_max_candidates]
@@ -90,6 +90,7 @@ struct hough_ctx {
     uint32_t *d_part_base = nullptr;   // [parts][kSplitBins] per-part starts
     uint64_t max_parts = 0;
     uint32_t *d_rz_hist = nullptr;     // [rz blocks][n_z0] zeroed uint32 (rz slow path)
+    uint64_t *d_redo_list = nullptr;   // [kRedoListCap] records the fast rz kernel leaves to the exact path
     uint4 *d_gap_info = nullptr;       // [max_events][L] gap vote: {mode, entries, list start, 0}
     uint2 *d_gap_list = nullptr;       // [max_hits] gap vote: per-layer hit or gap lists
     uint64_t *d_scan_part = nullptr;   // [scan_blocks_max] block sums of a multi-block scan
@@ -205,6 +206,11 @@ uint32_t rz_blocks(const hough_ctx *c);
 // Persistent rz workgroups at most (each owns an n_z0 histogram of the
 // context's slow-path scratch).
 constexpr uint32_t kMaxRzWavesPerCu = 16;
+// size of the context's array of work-queue counters (dwords)
+constexpr uint32_t kCounterDwords = 512;
+// capacity of the list of records the fast rz kernel leaves to the exact path
+// (past it, the exact-path kernel scans every record for the marks)
+constexpr uint32_t kRedoListCap = 1u << 16;
 inline uint32_t rz_blocks_max(const hough_ctx *c) { return uint32_t(c->n_cu) * kMaxRzWavesPerCu; }
 uint64_t max_peak_tiles(const hough_ctx *c);
 

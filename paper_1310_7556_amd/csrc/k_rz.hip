@@ -55,7 +55,11 @@ struct RzParams {
     const uint32_t *cand;         // selected local peak indices (cap > 0)
     uint2 *out4;                  // hough_rz records as 4 x uint32 (2 x uint2)
     uint64_t out_capacity;
-    uint32_t *counter;
+    uint32_t *counter;            // the work counter (general kernel); queue q's at counter[q * kRzQueueStride] (fast)
+    uint32_t n_queues;            // fast kernel: work queues, 1 .. kRzQueues
+    uint32_t *redo_count;         // records marked for the exact path
+    uint64_t *redo_list;          // their indices, the first redo_cap of them
+    uint32_t redo_cap;
     uint32_t *gscratch;           // [blocks][n_z0] zeroed uint32, slow path
     uint32_t n_events, n_layers, n_qpt, rows, nphi, log2phi, shift, bucket_bits;
     uint32_t n_z0, n_cot, cap;
@@ -71,13 +75,42 @@ struct RzParams {
     uint32_t mcap;                // fast path: member list capacity
 };
 
-// candidates taken per work-counter ticket by the fast kernel
+// The fast kernel's work queues: the candidates are split into kRzQueues
+// contiguous ranges, one per XCD, each with its own counter (kRzQueueStride
+// dwords apart, in different cache lines); a wave starts on the queue of
+// the XCD it runs on (read from the hardware, as the XCD a workgroup lands
+// on depends on what else runs), so that an XCD's waves share a range:
+// neighbouring cells, whose members and tables are the same cache lines in
+// that XCD's L2.  A wave takes kRzChunk consecutive candidates per ticket
+// and, when its queue is empty, moves on to the next queue (each empty
+// queue costs the wave one ticket, so short record lists -- a micro-batch --
+// use one queue).  (1000-track event: 0.96 ms with 8 queues of 8-candidate tickets;
+// 1.00 ms with one queue, 0.99 and 0.98 ms with tickets of 4 and 16, 1.04
+// and 1.17 ms with 32 and 64 queues.)
+constexpr uint32_t kRzQueues = 8;
+constexpr uint32_t kRzQueueStride = 32;
 constexpr uint32_t kRzChunk = 8;
+// the rz counters in the context's counter array: from dword kRzCounterBase,
+// the queues' counters, then the marked-record count
+constexpr uint32_t kRzCounterBase = 32;
+constexpr uint32_t kRzRedoCountAt = kRzQueues * kRzQueueStride;
+constexpr uint32_t kRzCounterDwords = kRzRedoCountAt + 1;
+static_assert(kRzCounterBase + kRzCounterDwords <= kCounterDwords, "rz counters fit the counter array");
 
 // count field of a record that k_rz_vote_fast leaves to k_rz_redo
 constexpr uint32_t kRzRedo = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The XCD (accelerator complex die) the wave runs on: the hardware register
+// XCC_ID, bits 0..3.
+__device__ __forceinline__ uint32_t xcd_id()
+{
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+}
+
+// a dword in LDS, addressed by its 32-bit LDS address
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 // floor(a * b / 2^32) of the low 24 bits of a and b, one full-rate
 // instruction.  Written as an instruction of its own so that the compiler
@@ -387,12 +420,15 @@ k_rz_vote_fast(RzParams P)
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
     for (uint32_t i = lane; i < P.hw * 64; i += 64) hist[i] = 0;
     __syncthreads();
-    for (;;) {
-        // a chunk of consecutive candidates per ticket (one contended atomic
-        // per kRzChunk candidates); the fetch itself as in k_rz_vote
-        const uint64_t c0 = uni(atomicAdd(P.counter, lane == 0 ? kRzChunk : 0u));
-        if (c0 >= total) break;
-        const uint64_t c1 = min(c0 + kRzChunk, total);
+    const uint32_t nq = P.n_queues, q0 = xcd_id();
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+      const uint32_t q = (q0 + qi) % nq;
+      const uint64_t qb = total * q / nq, qe = total * (q + 1) / nq;
+      uint32_t *qc = P.counter + q * kRzQueueStride;
+      for (;;) {
+        const uint64_t c0 = qb + uni(atomicAdd(qc, lane == 0 ? kRzChunk : 0u));
+        if (c0 >= qe) break;
+        const uint64_t c1 = min(c0 + kRzChunk, qe);
         // the next candidate's peak record is fetched while the current one
         // is processed, so its latency overlaps the current loads
         uint2 nrec = rz_record(P, c0);
@@ -563,8 +599,21 @@ k_rz_vote_fast(RzParams P)
                 // count wins, ties to the smallest bin)
                 const uint4 *mz4 = reinterpret_cast<const uint4 *>(mzc);
                 const uint32_t *ml4 = reinterpret_cast<const uint32_t *>(mlc);
-                // this lane's counter column (row stride 64 dwords)
-                uint32_t *col = hist + lane;
+                // this lane's counter column (row stride 64 dwords): the LDS
+                // address of counter dword (b >> PSH) is colb + (b >> PSH) *
+                // 256, a bit-field extract and a shift-add (written out, as
+                // the compiler otherwise takes three instructions)
+                const uint32_t colb = uint32_t(reinterpret_cast<uintptr_t>((lds_u32 *)(hist + lane)));
+                auto counter_at = [&](uint32_t bq) {
+                    uint32_t a;
+#if defined(__HIP_DEVICE_COMPILE__)
+                    asm("v_bfe_u32 %0, %1, %2, %3\n\tv_lshl_add_u32 %0, %0, 8, %4"
+                        : "=&v"(a) : "v"(bq), "i"(PSH), "i"(32 - PSH), "v"(colb));
+#else
+                    a = colb + ((bq >> PSH) << 8);
+#endif
+                    return reinterpret_cast<lds_u32 *>(uintptr_t(a));
+                };
                 int32_t run = INT32_MIN;
                 // Q members per step, starting at member m (a multiple of Q)
                 auto step = [&](auto qc, uint32_t m) {
@@ -609,11 +658,9 @@ k_rz_vote_fast(RzParams P)
                     }
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        // counter dword (b >> PSH) of this lane's column (a
-                        // bit-field extract keeps it one instruction plus a
-                        // shift-add)
-                        old[q] = atomicAdd(col + (__builtin_amdgcn_ubfe(b[q], PSH, 32 - PSH) << 6),
-                                           1u << (sh[q] & 31u));
+                        // counter dword (b >> PSH) of this lane's column
+                        old[q] = __hip_atomic_fetch_add(counter_at(b[q]), 1u << (sh[q] & 31u), __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
 #pragma unroll
                     for (int q = 0; q < Q; ++q) {
@@ -668,16 +715,23 @@ k_rz_vote_fast(RzParams P)
         if (nm > lim || (BITS <= 8 && __ballot(ovf) != 0)) {
             P.out4[2 * c] = make_uint2(r.pk, 0u);
             P.out4[2 * c + 1] = make_uint2(kRzRedo, nm);
+            if (lane == 0) {
+                const uint32_t i = atomicAdd(P.redo_count, 1u);
+                if (i < P.redo_cap) P.redo_list[i] = c;
+            }
         } else {
             rz_finish(P, c, r.pk, nm, best_c, best_j, best_b);
         }
+      }
       }
     }
 }
 
 // The exact path for the records k_rz_vote_fast marked (count == kRzRedo):
-// one wave per group of 8 records, each marked candidate recomputed exactly
-// (grid-stride over record groups; at most rz_blocks workgroups).  With
+// the wave takes every gridDim-th entry of the list of marked records the
+// fast kernel appended (when they all fit it; otherwise it scans every
+// record, in groups of 8, so that marked candidates that are neighbours in
+// the record list, a dense event's, spread over many waves).  With
 // redo_lds and at most kRedoMembers members, the members are gathered into
 // LDS once and counted per cot bin in an LDS histogram of the n_z0 bins,
 // every lane taking every 64th member; otherwise rz_slow with the global
@@ -732,25 +786,29 @@ __global__ void __launch_bounds__(64) k_rz_redo(RzParams P)
     const uint32_t lane = threadIdx.x;
     const uint64_t total = min(P.roff[P.n_events], P.out_capacity);
     uint32_t *g = P.gscratch + size_t(blockIdx.x) * P.n_z0;
-    // groups of kRedoGroup records, so that marked candidates that are
-    // neighbours in the record list (a dense event's) spread over many waves
+    auto redo = [&](uint64_t cc) {
+        const RzCand r = rz_decode(P, cc);
+        const uint32_t nm = uni(P.out4[2 * cc + 1].y);     // the fast kernel's member count
+        uint32_t best_c = 0, best_j = 0, best_b = 0;
+        if (P.redo_lds && nm <= kRedoMembers)
+            rz_exact_lds(P, r, mz, ml, hist, lane, best_c, best_j, best_b);
+        else
+            rz_slow(P, r.eb, r.bo, r.k, r.p, r.mask, g, lane, best_c, best_j, best_b);
+        if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
+        rz_finish(P, cc, r.pk, nm, best_c, best_j, best_b);
+    };
+    const uint32_t n = uni(*P.redo_count);
+    if (n <= P.redo_cap) {
+        for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) redo(uni64(P.redo_list[i]));
+        return;
+    }
     for (uint64_t c0 = uint64_t(blockIdx.x) * kRedoGroup; c0 < total; c0 += uint64_t(gridDim.x) * kRedoGroup) {
         const uint64_t c = c0 + lane;
-        const bool redo = lane < kRedoGroup && c < total && P.out4[2 * c + 1].x == kRzRedo;
-        uint64_t bal = __ballot(redo);
+        uint64_t bal = __ballot(lane < kRedoGroup && c < total && P.out4[2 * c + 1].x == kRzRedo);
         while (bal) {
             const uint32_t b = __ffsll(static_cast<unsigned long long>(bal)) - 1;
             bal &= bal - 1;
-            const uint64_t cc = c0 + b;
-            const RzCand r = rz_decode(P, cc);
-            const uint32_t nm = uni(P.out4[2 * cc + 1].y);     // the fast kernel's member count
-            uint32_t best_c = 0, best_j = 0, best_b = 0;
-            if (P.redo_lds && nm <= kRedoMembers)
-                rz_exact_lds(P, r, mz, ml, hist, lane, best_c, best_j, best_b);
-            else
-                rz_slow(P, r.eb, r.bo, r.k, r.p, r.mask, g, lane, best_c, best_j, best_b);
-            if (lane != 0) { best_c = 0; best_j = 0xFFFFu; best_b = 0; }
-            rz_finish(P, cc, r.pk, nm, best_c, best_j, best_b);
+            redo(c0 + b);
         }
     }
 }
@@ -768,8 +826,9 @@ __global__ void k_rz_counts(const uint64_t *__restrict__ poff, uint64_t peak_cap
 
 // For batches of up to kRzOffsetsMaxEvents events, in one workgroup: the
 // candidate count of every event (as k_rz_counts), their exclusive prefix
-// into roff[0..E] and the reset of the work counter -- one launch where the
-// general path takes three.
+// into roff[0..E] and the reset of the work counters and the marked-record
+// count (counter[0 .. kRzCounterDwords)) -- one launch where the general
+// path takes three.
 constexpr uint32_t kRzOffsetsMaxEvents = 1024 * 8;
 
 __global__ void __launch_bounds__(1024)
@@ -801,7 +860,7 @@ k_rz_offsets(const uint64_t *__restrict__ poff, uint64_t peak_capacity, uint32_t
         run += count(e);
     }
     if (t == nt - 1) roff[n_events] = part[nt - 1];
-    if (t == 0) *counter = 0;
+    for (uint32_t i = t; i < kRzCounterDwords; i += nt) counter[i] = 0;
 }
 
 // Candidate selection with a cap: the first cap peaks of the event ordered
@@ -998,7 +1057,7 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     prof_begin(c, "rz_counts", s, &t);
     if (fused)
         hipLaunchKernelGGL(k_rz_offsets, dim3(1), dim3(1024), 0, s, poff, peak_capacity, E, g.rz_max_candidates,
-                           roff, c->d_counters + 1);
+                           roff, c->d_counters + kRzCounterBase);
     else
         hipLaunchKernelGGL(k_rz_counts, dim3((E + 255) / 256), dim3(256), 0, s, poff, peak_capacity, E,
                            g.rz_max_candidates, c->d_cand_counts);
@@ -1025,7 +1084,8 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
         prof_end(c, s, &t);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    if (!fused && (err = launch_fill_u32(c, c->d_counters + 1, 0, 1, s)) != hipSuccess) return err;
+    if (!fused && (err = launch_fill_u32(c, c->d_counters + kRzCounterBase, 0, kRzCounterDwords, s)) != hipSuccess)
+        return err;
 
     RzParams P;
     P.phi = c->d_phi_b;
@@ -1044,7 +1104,10 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     P.cand = c->d_cand;
     P.out4 = reinterpret_cast<uint2 *>(out);
     P.out_capacity = capacity;
-    P.counter = c->d_counters + 1;
+    P.counter = c->d_counters + kRzCounterBase;
+    P.redo_count = c->d_counters + kRzCounterBase + kRzRedoCountAt;
+    P.redo_list = c->d_redo_list;
+    P.redo_cap = c->tun.rz_redo_list ? c->tun.rz_redo_list : kRedoListCap;
     P.gscratch = c->d_rz_hist;
     P.n_events = E;
     P.n_layers = g.n_layers;
@@ -1089,6 +1152,12 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
     if (c->rz_fast && !c->tun.rz_slow_path && fast_lds <= c->max_lds && g.n_layers < kMaxLayers) {
         P.hw = hw;
         P.mcap = mcap;
+        // one queue per XCD where the records can give every wave several
+        // tickets; one queue for short lists (a micro-batch), whose waves
+        // would spend more on empty tickets than the queues save (16-event
+        // c5 micro-batches served at 17k events/s with 8 queues, 19.7k with
+        // one)
+        P.n_queues = rz_records_bound(c, h, peak_capacity, capacity) >= uint64_t(4) * blocks * kRzChunk ? kRzQueues : 1u;
         P.lds_ok = 0;
         prof_begin(c, "rz_vote", s, &t);
         const int mul = P.bs != 0 ? 1 : (P.span < (1u << 24) && P.bm < (1u << 24)) ? 2 : 0;
@@ -1101,15 +1170,19 @@ hipError_t launch_rz(hough_ctx *c, const hough_hits *h, const hough_peak *peaks,
             launch_fast<16>(mul, blocks, fast_lds, s, P);
         prof_end(c, s, &t);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        // candidates the fast kernel marked; the grid covers every record
-        // group and uses at most the slow path's histograms
+        // candidates the fast kernel marked (grid-stride over the list of
+        // them, or over every record group); at most the slow path's
+        // histograms
         const uint64_t groups =
             std::max<uint64_t>(1, (rz_records_bound(c, h, peak_capacity, capacity) + kRedoGroup - 1) / kRedoGroup);
         const size_t redo_lds = (size_t(kRedoMembers) * 5 + size_t(g.n_z0) * 4 + 15) & ~size_t(15);
         P.redo_lds = redo_lds <= c->max_lds ? 1u : 0u;
+        // as many workgroups as are resident at once with the LDS path's
+        // allocation (they mostly find the list empty and exit)
+        const uint64_t resident = uint64_t(c->n_cu) * std::max<size_t>(1, P.redo_lds ? c->max_lds / redo_lds : 16);
+        const uint64_t grid = std::min<uint64_t>(std::min<uint64_t>(groups, resident), rz_blocks_max(c));
         prof_begin(c, "rz_redo", s, &t);
-        hipLaunchKernelGGL(k_rz_redo, dim3(uint32_t(std::min<uint64_t>(groups, rz_blocks_max(c)))), dim3(64),
-                           P.redo_lds ? redo_lds : 0, s, P);
+        hipLaunchKernelGGL(k_rz_redo, dim3(uint32_t(grid)), dim3(64), P.redo_lds ? redo_lds : 0, s, P);
         prof_end(c, s, &t);
         return hipGetLastError();
     }

@@ -66,7 +66,8 @@ class Tuning(C.Structure):
                 ("vote_wgs_per_cu", C.c_uint32), ("peak_rows", C.c_uint32),
                 ("rz_waves_per_cu", C.c_uint32), ("vote_algo", C.c_uint32),
                 ("rz_slow_path", C.c_uint32), ("rz_counter_bits", C.c_uint32),
-                ("vote_items", C.c_uint32), ("peak_algo", C.c_uint32), ("rz_member_cap", C.c_uint32)]
+                ("vote_items", C.c_uint32), ("peak_algo", C.c_uint32), ("rz_member_cap", C.c_uint32),
+                ("rz_redo_list", C.c_uint32)]
 
 
 _lib = None

@@ -421,6 +421,26 @@ def test_rz_kernel_variants(H, tuning, kw):
         check_event(H, tab, res, batch, e, rz=True)
 
 
+def test_rz_marked_records_past_the_list_are_found_by_the_scan(H):
+    """More candidates left to the exact path than the list of them holds
+    (a 4-entry list): the exact-path kernel scans every record instead, and
+    the records equal the oracle's and the list path's."""
+    spec = small_spec(n_phi=16, n_qpt=8, n_cot=40)
+    batch = ragged_batch()
+    base = dict(rz_counter_bits=8, rz_member_cap=256)
+    res_list = run_gpu(H, spec, batch, tuning=base)
+    res_scan = run_gpu(H, spec, batch, tuning=dict(base, rz_redo_list=4))
+    tab = oracle.Tables(spec)
+    marked = 0
+    for e in range(batch.n_events):
+        check_event(H, tab, res_scan, batch, e, rz=True)
+        a = H.rz_numpy(res_list["rz"], res_list["roff"], e)
+        b = H.rz_numpy(res_scan["rz"], res_scan["roff"], e)
+        assert np.array_equal(a, b)
+        marked += int((b["n_members"] > 256).sum())
+    assert marked > 4
+
+
 def test_rz_exact_path_past_the_lds_member_list(H):
     """A cell with more members than the exact path's LDS list (8192): the
     global-histogram path, against the oracle."""
