@@ -686,16 +686,21 @@ k_rz_vote_fast(RzParams P)
                 // a count of FIELD + 1 can only come from a vote that found
                 // its field full: the counter overflowed
                 if (BITS <= 8) ovf = ovf || bc > FIELD;
-                // clear all counters, 16 bytes per lane per store; a store
+                // clear the counters, 16 bytes per lane per store; a store
                 // covers other lanes' columns, so every lane's counting must
                 // be finished first and the clear finished before the next
-                // cot bins are counted (nothing to clear after an empty pass)
+                // cot bins are counted (nothing to clear after an empty pass).
+                // The clear bounds the kernel (8 KB per pass through the LDS,
+                // 0.15 ms of the 1000-track event's 0.96 ms), so a trash bin
+                // alone in the last counter dword is left as it is: its count
+                // is never read.  (Zeroing just the dwords the votes went to,
+                // the members' bins recomputed, costs more: 1.01 ms.)
                 if (nq) {
                     __syncthreads();
                     // full rounds of 64 16-byte stores at fixed offsets from
                     // one address, then the partial last round
                     uint4 *h4 = reinterpret_cast<uint4 *>(hist) + lane;
-                    const uint32_t n4 = P.hw * 16, full = n4 >> 6;
+                    const uint32_t n4 = (P.hw - (P.n_z0 % PACK == 0 ? 1u : 0u)) * 16, full = n4 >> 6;
 #pragma unroll 8
                     for (uint32_t k = 0; k < full; ++k) h4[k * 64] = make_uint4(0u, 0u, 0u, 0u);
                     if (lane < (n4 & 63u)) h4[full * 64] = make_uint4(0u, 0u, 0u, 0u);
