@@ -122,10 +122,10 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
     uint32_t &n_ivl = *(srt + L * kRankSortStride + (L * nphi + 1) / 2);       // the list's length
 
     if (BOUNDS) {
-        for (uint32_t i = t; i < L * nphi; i += nt) {
-            bmin[i] = 0xFFFFFFFFu;
-            bmax[i] = 0u;
-        }
+        // 16-byte stores (L * nphi is a multiple of 4; bmin is 16-byte aligned)
+        uint4 *b4 = reinterpret_cast<uint4 *>(bmin);
+        for (uint32_t i = t; i < L * nphi / 2; i += nt)
+            b4[i] = i < L * nphi / 4 ? make_uint4(~0u, ~0u, ~0u, ~0u) : make_uint4(0u, 0u, 0u, 0u);
         __syncthreads();
         const uint64_t b = min(offs[e], n_hits);
         uint64_t end = min(offs[e + 1], n_hits);
@@ -186,12 +186,31 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
     }
 
     uint16_t *eacc = acc + uint64_t(e) * rows * nphi;
+    // a tile's sorted offsets are loaded into registers one tile ahead (the
+    // loads are in flight while the previous tile is ranked and voted) and
+    // stored to LDS when that tile is done
+    constexpr uint32_t kSrtRegs = (16 * kRankSortStride + kRankThreads - 1) / kRankThreads;
+    const uint32_t n_srt = L * kRankSortStride;
+    uint32_t sp[kSrtRegs];
+    auto srt_load = [&](uint32_t tl) {
+        const uint32_t *gs = rk_sorted + size_t(tl) * n_srt;
+#pragma unroll
+        for (uint32_t k = 0; k < kSrtRegs; ++k) {
+            const uint32_t i = t + k * kRankThreads;
+            sp[k] = i < n_srt ? gs[i] : 0u;
+        }
+    };
+    if (tile_lo < tile_hi) srt_load(tile_lo);
     for (uint32_t tile = tile_lo; tile < tile_hi; ++tile) {
         // previous tile's rows are done with the byte tables; the list is complete
         __syncthreads();
-        const uint32_t *gs = rk_sorted + size_t(tile) * L * kRankSortStride;
-        for (uint32_t i = t; i < L * kRankSortStride; i += nt) srt[i] = gs[i];
+#pragma unroll
+        for (uint32_t k = 0; k < kSrtRegs; ++k) {
+            const uint32_t i = t + k * kRankThreads;
+            if (i < n_srt) srt[i] = sp[k];
+        }
         __syncthreads();
+        if (tile + 1 < tile_hi) srt_load(tile + 1);
         // (a, span) bytes of the listed entries for this tile
         const uint32_t nl_ivl = n_ivl;
         for (uint32_t q = t; q < nl_ivl; q += nt) {
