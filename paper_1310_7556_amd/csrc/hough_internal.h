@@ -28,10 +28,14 @@ constexpr uint32_t kMaxBucketBits = 12;
 constexpr size_t kOPad = 64;
 
 // Rank form of the vote: rows per tile (ranks fit a byte), workgroup size
-// and the stride of a tile's sorted fine offsets (128 values + padding).
+// and the stride of a tile's sorted fine offsets per layer: 128 values +
+// padding, then a search index (kRankIndexAt: the smallest and largest
+// value, a shift, the count, and 257 byte counts of the values below each of
+// 256 equal parts of [smallest, largest]).
 constexpr uint32_t kRankTileRows = 128;
 constexpr uint32_t kRankThreads = 512;
-constexpr uint32_t kRankSortStride = 132;
+constexpr uint32_t kRankIndexAt = 132;
+constexpr uint32_t kRankSortStride = kRankIndexAt + 4 + 68;
 
 struct KernelTimer {
     const char *name;

@@ -74,14 +74,26 @@ __device__ __forceinline__ void rank_event_hits(const uint8_t *__restrict__ laye
     for (uint64_t i = tail + t; i < end; i += nt) f(uint32_t(layer[i]), phi[i]);
 }
 
-// #{s[k] < x} over a tile's sorted fine offsets s[0..128] (padded with
-// 0xFFFFFFFF, larger than any x used here).
+// #{s[k] < x} over a tile's sorted fine offsets s[0..count) and their
+// index (kRankIndexAt: smallest f0, largest f1, shift sh, count, then the
+// bytes ix[b] = #{s < f0 + b 2^sh}, b = 0..256): outside [f0, f1] the rank
+// is 0 or count; inside, part b = (x - f0) >> sh narrows it to [ix[b],
+// ix[b + 1]), searched by bisection (one or two values on average, where a
+// bisection of all 128 takes eight dependent reads).
 __device__ __forceinline__ uint32_t rank_below(const uint32_t *s, uint32_t x)
 {
-    uint32_t pos = 0;
-#pragma unroll
-    for (uint32_t step = 64; step > 0; step >>= 1) pos += s[pos + step - 1] < x ? step : 0u;
-    return pos + (s[pos] < x ? 1u : 0u);
+    const uint32_t f0 = s[kRankIndexAt], f1 = s[kRankIndexAt + 1], sh = s[kRankIndexAt + 2];
+    const uint32_t cnt = s[kRankIndexAt + 3];
+    if (cnt == 0 || x <= f0) return 0;
+    if (x > f1) return cnt;
+    const uint8_t *ix = reinterpret_cast<const uint8_t *>(s + kRankIndexAt + 4);
+    const uint32_t b = (x - f0) >> sh;
+    uint32_t lo = ix[b], hi = ix[b + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
 }
 
 }  // namespace
@@ -113,13 +125,28 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
     const uint32_t tile_lo = (item % runs_per_event) * run_tiles;
     const uint32_t tile_hi = min(n_tiles, tile_lo + run_tiles);
 
-    // LDS: [bmin | bmax] (BOUNDS), the byte tables, the tile's sorted
-    // offsets, the list of (layer, bucket) entries that can be empty, its length
-    uint32_t *bmin = lds, *bmax = lds + (BOUNDS ? L * nphi : 0);
-    uint32_t *bytes = lds + (BOUNDS ? 2 * L * nphi : 0);         // [L][ngrp + 1] x {a word, span word}
-    uint32_t *srt = bytes + L * (ngrp + 1) * 2;                  // [L][kRankSortStride]
-    uint16_t *ivl = reinterpret_cast<uint16_t *>(srt + L * kRankSortStride);   // [L * nphi]
-    uint32_t &n_ivl = *(srt + L * kRankSortStride + (L * nphi + 1) / 2);       // the list's length
+    // LDS.  Tile items (!BOUNDS): the byte tables, the tile's sorted
+    // offsets, the list of (layer, bucket) entries that can be empty, its
+    // length.  Event items (BOUNDS): [bmin | bmax] (N = L * nphi entries
+    // each) while the bounds are found; then, over the same bytes, every
+    // entry's interval packed in 6 bytes (three uint16 arrays: low halves of
+    // lo and hi, then their high bytes), the byte tables and the sorted
+    // offsets -- 8 N + 536 L bytes where the list form took 12 N + 536 L
+    // (46 against 66 KB for ten layers of 512 bins: three workgroups per CU
+    // instead of two).
+    const uint32_t N = L * nphi;
+    uint32_t *bmin = lds, *bmax = lds + (BOUNDS ? N : 0);
+    uint16_t *p_lo = reinterpret_cast<uint16_t *>(lds);           // BOUNDS: [N] lo & 0xFFFF
+    uint16_t *p_hi = p_lo + N;                                    //         [N] hi & 0xFFFF
+    uint16_t *p_hb = p_hi + N;                                    //         [N] lo >> 16 | (hi >> 16) << 8
+    uint32_t *bytes = lds + (BOUNDS ? 3 * N / 2 : 0);             // [L][ngrp + 1] x {a word, span word}
+    uint32_t *srt = bytes + L * (ngrp + 1) * 2;                   // [L][kRankSortStride]
+    uint16_t *ivl = reinterpret_cast<uint16_t *>(srt + L * kRankSortStride);   // !BOUNDS: [N]
+    uint32_t &n_ivl = *(srt + L * kRankSortStride + (N + 1) / 2);              // !BOUNDS: the list's length
+    // BOUNDS: the entries i = t + k * kRankThreads (k < EPT) of this thread,
+    // bit k set when entry i has an interval
+    constexpr uint32_t EPT = (LMAX * 256 * G + kRankThreads - 1) / kRankThreads;   // n_phi = 256 G
+    uint32_t has_bits = 0;
 
     if (BOUNDS) {
         // 16-byte stores (L * nphi is a multiple of 4; bmin is 16-byte aligned)
@@ -154,10 +181,36 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             hi = v.x == 0xFFFFFFFFu ? 0u : v.x + v.y;
         }
     };
-    // Once per item: the entries with an interval (about a fifth of the
-    // buckets of a dense layer) go to a list, every byte-table entry starts
-    // at (a, span) = (0, 0), never empty, and only listed entries are
-    // ranked per tile.
+    // Once per item: every byte-table entry starts at (a, span) = (0, 0),
+    // never empty, and only entries with an interval (about a fifth of the
+    // buckets of a dense layer) are ranked per tile: event items keep each
+    // thread's entries' intervals packed in LDS (read into registers first,
+    // as they overwrite the bounds), tile items list the entries.
+    if (BOUNDS) {
+        __syncthreads();                                 // every hit's bounds update done
+        uint32_t lo_r[EPT], hi_r[EPT];
+#pragma unroll
+        for (uint32_t k = 0; k < EPT; ++k) {
+            const uint32_t i = t + k * kRankThreads;
+            lo_r[k] = 1;
+            hi_r[k] = 0;
+            if (i < N) interval(i, lo_r[k], hi_r[k]);
+        }
+        __syncthreads();                                 // every bound read before any is overwritten
+#pragma unroll
+        for (uint32_t k = 0; k < EPT; ++k) {
+            const uint32_t i = t + k * kRankThreads;
+            if (i < N) {
+                const bool h = lo_r[k] <= hi_r[k];       // then both are below 2^24
+                has_bits |= h ? 1u << k : 0u;
+                p_lo[i] = uint16_t(lo_r[k]);
+                p_hi[i] = uint16_t(hi_r[k]);
+                p_hb[i] = h ? uint16_t((lo_r[k] >> 16) | ((hi_r[k] >> 16) << 8)) : uint16_t(0);
+            }
+        }
+        for (uint32_t i = t; i < L * (ngrp + 1) * 2; i += nt) bytes[i] = 0u;
+        __syncthreads();
+    } else {
     if (t == 0) n_ivl = 0;
     for (uint32_t i = t; i < L * (ngrp + 1) * 2; i += nt) bytes[i] = 0u;
     __syncthreads();
@@ -183,6 +236,7 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             base = __shfl(base, 0, 64);
             if (has[u]) ivl[base + __popcll(bal & ((1ull << lane) - 1ull))] = uint16_t(i);
         }
+    }
     }
 
     uint16_t *eacc = acc + uint64_t(e) * rows * nphi;
@@ -211,13 +265,9 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
         }
         __syncthreads();
         if (tile + 1 < tile_hi) srt_load(tile + 1);
-        // (a, span) bytes of the listed entries for this tile
-        const uint32_t nl_ivl = n_ivl;
-        for (uint32_t q = t; q < nl_ivl; q += nt) {
-            const uint32_t i = ivl[q];
+        // (a, span) bytes of the entries with an interval for this tile
+        auto rank_entry = [&](uint32_t i, uint32_t lo, uint32_t hi) {
             const uint32_t l = i >> log2phi, j = i & (nphi - 1);
-            uint32_t lo, hi;
-            interval(i, lo, hi);
             const uint32_t *sl = srt + l * kRankSortStride;
             const uint32_t a = rank_below(sl, lo);
             const uint32_t sp = rank_below(sl, hi + 1u) - a;
@@ -228,6 +278,24 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             if (g == 0) {                                   // wrap group: buckets n_phi .. n_phi + 3
                 bl[ngrp * 8 + k] = uint8_t(a);
                 bl[ngrp * 8 + 4 + k] = uint8_t(sp);
+            }
+        };
+        if (BOUNDS) {
+#pragma unroll 1
+            for (uint32_t k = 0; k < EPT; ++k) {
+                if ((has_bits >> k) & 1u) {
+                    const uint32_t i = t + k * kRankThreads;
+                    const uint32_t hb = p_hb[i];
+                    rank_entry(i, uint32_t(p_lo[i]) | ((hb & 0xFFu) << 16), uint32_t(p_hi[i]) | ((hb >> 8) << 16));
+                }
+            }
+        } else {
+            const uint32_t nl_ivl = n_ivl;
+            for (uint32_t q = t; q < nl_ivl; q += nt) {
+                const uint32_t i = ivl[q];
+                uint32_t lo, hi;
+                interval(i, lo, hi);
+                rank_entry(i, lo, hi);
             }
         }
         __syncthreads();
@@ -349,9 +417,10 @@ void launch_rank(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint32
 
 size_t rank_lds_bytes(const hough_ctx *c, bool bounds)
 {
-    const size_t L = c->spec.n_layers, nphi = c->spec.n_phi;
-    return (bounds ? 2 * L * nphi * 4 : 0) + L * (nphi / 4 + 1) * 8 + L * kRankSortStride * 4 +
-           ((L * nphi + 1) / 2) * 4 + 4;
+    const size_t L = c->spec.n_layers, nphi = c->spec.n_phi, N = L * nphi;
+    const size_t tables = L * (nphi / 4 + 1) * 8 + L * kRankSortStride * 4;
+    if (bounds) return std::max(8 * N, 6 * N + tables);       // the bounds, then the packed intervals and tables
+    return tables + ((N + 1) / 2) * 4 + 4;
 }
 
 }  // namespace
@@ -376,7 +445,23 @@ void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, 
             f.clear();
             for (uint32_t r = r0; r < r1; ++r) f.push_back(O[size_t(l) * rows + r] & wmask);
             std::sort(f.begin(), f.end());
-            std::copy(f.begin(), f.end(), sorted.begin() + (size_t(t) * L + l) * kRankSortStride);
+            uint32_t *st = sorted.data() + (size_t(t) * L + l) * kRankSortStride;
+            std::copy(f.begin(), f.end(), st);
+            // the search index of these values (see rank_below)
+            const uint32_t f0 = f.empty() ? 0u : f.front(), f1 = f.empty() ? 0u : f.back();
+            uint32_t sh = 0;
+            while (((f1 - f0) >> sh) > 255u) ++sh;
+            st[kRankIndexAt] = f0;
+            st[kRankIndexAt + 1] = f1;
+            st[kRankIndexAt + 2] = sh;
+            st[kRankIndexAt + 3] = uint32_t(f.size());
+            uint8_t *ix = reinterpret_cast<uint8_t *>(st + kRankIndexAt + 4);
+            for (uint32_t b = 0; b <= 256; ++b) {
+                const uint64_t edge = uint64_t(f0) + (uint64_t(b) << sh);
+                ix[b] = uint8_t(std::lower_bound(f.begin(), f.end(), edge,
+                                                 [](uint32_t v, uint64_t e) { return uint64_t(v) < e; }) -
+                                f.begin());
+            }
             for (uint32_t r = r0; r < r1; ++r) {
                 const uint32_t o = O[size_t(l) * rows + r];
                 const uint32_t rank = uint32_t(std::lower_bound(f.begin(), f.end(), o & wmask) - f.begin());
