@@ -95,7 +95,8 @@ constexpr uint32_t kRzChunk = 8;
 // Passes with at most kRzSortMax members are counted by sorting each lane's
 // bins with a sorting network, 8 or 12 inputs: 19 and 39 comparators (both
 // minimal in size; each checked on every 0-1 input, which by the 0-1
-// principle shows that it sorts every input).  Where most passes have 12
+// principle shows that it sorts every input; so are their restrictions to
+// fewer inputs, the rest held above every value).  Where most passes have 12
 // members or fewer (the 1000-track event: 76%, a third 8 or fewer) this
 // replaces most counter atomics and clears: rz 0.95 -> 0.89 ms (0.92 with
 // 8-input sorts only; 0.91 with a 16-input network added for up to 16).
@@ -696,19 +697,25 @@ k_rz_vote_fast(RzParams P)
                 // longest, as the counters give -- so the counters are
                 // neither touched nor cleared.
                 uint32_t bc = 0, bb = 0;
-                auto sorted_pass = [&](auto nc) {
-                    constexpr int NS = decltype(nc)::value;
-                    uint32_t v[NS];
+                // M (= nq, a constant of the instance) members: the inputs
+                // past M are constants above every bin, so the compiler
+                // drops the comparators and sweep steps they would take part
+                // in (the 8- or 12-input network restricted to M inputs:
+                // 5, 9, 12, 16, 19, 26, 30, 35, 39 comparators for M = 4..12)
+                auto sorted_pass = [&](auto mc) {
+                    constexpr int M = decltype(mc)::value;
+                    constexpr int N = M <= 8 ? 8 : 12;
+                    uint32_t v[N];
 #pragma unroll
-                    for (int g = 0; g < NS / 4; ++g) {
+                    for (int q = M; q < N; ++q) v[q] = 0xFFFFFFFFu;
+#pragma unroll
+                    for (int g = 0; g < (M + 3) / 4; ++g) {
                         const uint4 z4 = mz4[g];
                         const uint32_t lw = uni(ml4[g]);
                         const uint32_t zq[4] = {z4.x, z4.y, z4.z, z4.w};
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const uint32_t q = uint32_t(4 * g + i);
-                            const uint32_t lq = q < nq ? (lw >> (8 * i)) & 0xFFu : 0u;
-                            const uint32_t u = q < nq ? zq[i] - zc[lq] : 0xFFFFFFFFu;
+                        for (int i = 0; i < 4 && 4 * g + i < M; ++i) {
+                            const uint32_t u = zq[i] - zc[(lw >> (8 * i)) & 0xFFu];
                             if (MUL == 2) {
                                 v[4 * g + i] = mulhi_u24(P.bm, min(u, P.span24));
                             } else {
@@ -718,9 +725,9 @@ k_rz_vote_fast(RzParams P)
                             }
                         }
                     }
-                    // a sorting network, ascending
-                    const auto &net = NS == 8 ? kSortNet8 : kSortNet12;
-                    constexpr int NC = NS == 8 ? kSortNet8Size : kSortNet12Size;
+                    // the sorting network, ascending
+                    const auto &net = N == 8 ? kSortNet8 : kSortNet12;
+                    constexpr int NC = N == 8 ? kSortNet8Size : kSortNet12Size;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         const uint32_t a = v[net[c][0]], b2 = v[net[c][1]];
@@ -733,7 +740,7 @@ k_rz_vote_fast(RzParams P)
                         bb = v[0];
                     }
 #pragma unroll
-                    for (int i = 1; i < NS; ++i) {
+                    for (int i = 1; i < M; ++i) {
                         cnt = v[i] == v[i - 1] ? cnt + 1 : 1u;
                         if (v[i] < P.n_z0 && cnt > bc) {
                             bc = cnt;
@@ -742,10 +749,23 @@ k_rz_vote_fast(RzParams P)
                     }
                 };
                 const bool sorted = nq <= kRzSortMax;
-                if (nq <= 8) {
-                    sorted_pass(std::integral_constant<int, 8>{});
-                } else if (sorted) {
-                    sorted_pass(std::integral_constant<int, 12>{});
+                if (sorted) {
+                    using std::integral_constant;
+                    switch (nq) {
+                    case 0: break;
+                    case 1: sorted_pass(integral_constant<int, 1>{}); break;
+                    case 2: sorted_pass(integral_constant<int, 2>{}); break;
+                    case 3: sorted_pass(integral_constant<int, 3>{}); break;
+                    case 4: sorted_pass(integral_constant<int, 4>{}); break;
+                    case 5: sorted_pass(integral_constant<int, 5>{}); break;
+                    case 6: sorted_pass(integral_constant<int, 6>{}); break;
+                    case 7: sorted_pass(integral_constant<int, 7>{}); break;
+                    case 8: sorted_pass(integral_constant<int, 8>{}); break;
+                    case 9: sorted_pass(integral_constant<int, 9>{}); break;
+                    case 10: sorted_pass(integral_constant<int, 10>{}); break;
+                    case 11: sorted_pass(integral_constant<int, 11>{}); break;
+                    default: sorted_pass(integral_constant<int, 12>{}); break;
+                    }
                 } else {
                     uint32_t m = 0;
                     for (; m + 8 <= nq; m += 8) step(std::integral_constant<int, 8>{}, m);
