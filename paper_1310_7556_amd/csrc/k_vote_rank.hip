@@ -281,13 +281,12 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             }
         };
         if (BOUNDS) {
-#pragma unroll 1
-            for (uint32_t k = 0; k < EPT; ++k) {
-                if ((has_bits >> k) & 1u) {
-                    const uint32_t i = t + k * kRankThreads;
-                    const uint32_t hb = p_hb[i];
-                    rank_entry(i, uint32_t(p_lo[i]) | ((hb & 0xFFu) << 16), uint32_t(p_hi[i]) | ((hb >> 8) << 16));
-                }
+            // each lane walks its own entries with an interval (the wave
+            // takes as many steps as its busiest lane has entries)
+            for (uint32_t bits = has_bits; bits; bits &= bits - 1u) {
+                const uint32_t i = t + uint32_t(__builtin_ctz(bits)) * kRankThreads;
+                const uint32_t hb = p_hb[i];
+                rank_entry(i, uint32_t(p_lo[i]) | ((hb & 0xFFu) << 16), uint32_t(p_hi[i]) | ((hb >> 8) << 16));
             }
         } else {
             const uint32_t nl_ivl = n_ivl;
