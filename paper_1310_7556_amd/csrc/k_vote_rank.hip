@@ -377,7 +377,10 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
                 uint2 out;
                 out.x = __builtin_amdgcn_perm(m2[g], m1[g], 0x05010400u);
                 out.y = __builtin_amdgcn_perm(m2[g], m1[g], 0x07030602u);
-                *reinterpret_cast<uint2 *>(dst + 256u * g + 4u * lane) = out;
+                // written once and read back by the peak search long after:
+                // a non-temporal store (c4 vote 0.73 -> 0.72 ms)
+                __builtin_nontemporal_store(uint64_t(out.x) | (uint64_t(out.y) << 32),
+                                            reinterpret_cast<uint64_t *>(dst + 256u * g + 4u * lane));
             }
         }
     }
