@@ -662,3 +662,28 @@ def test_cluster_fit_without_bucket_index_is_refused(H):
     cl, coff = ctx.new_clusters(16), ctx.new_offsets(1)
     with pytest.raises(H.HoughError, match="invalid argument"):
         ctx.cluster_fit(hits, pk, poff, cl, coff, peak_capacity=16, capacity=16)
+
+
+@pytest.mark.parametrize("n_layers", [7, 13, 16])
+@pytest.mark.parametrize("tuning", [None, dict(vote_algo=5, vote_items=1), dict(vote_algo=5, vote_items=2),
+                                    dict(vote_algo=4), dict(peak_algo=1), dict(rz_counter_bits=8)])
+def test_other_layer_counts(H, n_layers, tuning):
+    """Detectors of 7, 13 and 16 layers (the kernels' general layer-count
+    instances; every other test uses ten): accumulators, peaks and rz
+    records of ragged events against the oracle, under the vote forms (rank
+    form with whole events and with single tiles, direct form), both peak
+    forms and 8-bit rz counters."""
+    radii = [40.0 + (800.0 - 40.0) * i / (n_layers - 1) for i in range(n_layers)]
+    spec = small_spec(n_layers=n_layers, layer_r_mm=radii, threshold=min(8, n_layers - 2), n_phi=256)
+    evs = []
+    for e, n in enumerate([0, 5, 300, 1200, 4000, 1]):
+        rng = np.random.default_rng(700 + e)
+        layer = rng.integers(0, n_layers, n).astype(np.uint8)
+        layer[::53] = n_layers + 2                   # out-of-range layers are ignored
+        evs.append((layer, rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
+                    rng.integers(-1_200_000, 1_200_000, n).astype(np.int32)))
+    batch = synth.concat_events(evs)
+    res = run_gpu(H, spec, batch, tuning=tuning)
+    tab = oracle.Tables(spec)
+    for e in range(batch.n_events):
+        check_event(H, tab, res, batch, e, rz=True)
