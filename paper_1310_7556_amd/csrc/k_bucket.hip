@@ -262,13 +262,21 @@ k_event_order(const uint64_t *__restrict__ offs, uint64_t n_hits, uint32_t n_eve
     __syncthreads();
     for (uint32_t e = t; e < n_events; e += blockDim.x) atomicAdd(&hist[key(e)], 1u);
     __syncthreads();
-    if (t == 0) {
-        uint32_t run = 0;
-        for (uint32_t i = 0; i < 256; ++i) {
-            const uint32_t x = hist[i];
-            hist[i] = run;
-            run += x;
+    // exclusive prefix sum of the 256 bins: four per lane of the first wave,
+    // then a wave scan of the lanes' totals
+    if (t < 64) {
+        const uint32_t h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
+        const uint32_t tot = h0 + h1 + h2 + h3;
+        uint32_t inc = tot;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(inc, d, 64);
+            if (t >= d) inc += v;
         }
+        const uint32_t ex = inc - tot;
+        hist[4 * t] = ex;
+        hist[4 * t + 1] = ex + h0;
+        hist[4 * t + 2] = ex + h0 + h1;
+        hist[4 * t + 3] = ex + h0 + h1 + h2;
     }
     __syncthreads();
     for (uint32_t e = t; e < n_events; e += blockDim.x) order[atomicAdd(&hist[key(e)], 1u)] = e;
