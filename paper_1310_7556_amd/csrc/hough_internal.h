@@ -37,6 +37,32 @@ constexpr uint32_t kRankThreads = 512;
 constexpr uint32_t kRankIndexAt = 132;
 constexpr uint32_t kRankSortStride = kRankIndexAt + 4 + 68;
 
+// Whole-event items rank each entry's interval once against all rows of its
+// layer.  Per layer, the fine offsets of every row sorted (from
+// kRankGlobAt), after a header (the smallest and largest value, a shift, the
+// count) and 257 16-bit counts of the values below each of 256 equal parts
+// of [smallest, largest]; per (tile, layer), the bytes cnt[k] = how many of
+// the first k sorted values belong to the tile, k = 0..rows.  Both follow
+// the per-tile tables in the same buffer; only grids of at most
+// kRankEventRowsMax rows have them.
+constexpr uint32_t kRankGlobAt = 4 + 129;
+constexpr uint32_t kRankEventRowsMax = 1024;
+struct RankGlobLayout {
+    size_t glob_at, cnt_at, size;   // in 32-bit words from the buffer's start
+    uint32_t gstride, cstride;      // per layer
+};
+inline RankGlobLayout rank_glob_layout(uint32_t rows, uint32_t L)
+{
+    RankGlobLayout y;
+    const size_t n_tiles = (rows + kRankTileRows - 1) / kRankTileRows;
+    y.gstride = (kRankGlobAt + rows + 3) & ~3u;
+    y.cstride = (rows + 1 + 3) / 4;
+    y.glob_at = n_tiles * L * kRankSortStride;
+    y.cnt_at = y.glob_at + size_t(L) * y.gstride;
+    y.size = rows <= kRankEventRowsMax ? y.cnt_at + n_tiles * L * y.cstride : y.glob_at;
+    return y;
+}
+
 struct KernelTimer {
     const char *name;
     hipEvent_t start, stop;
@@ -102,7 +128,8 @@ struct hough_ctx {
     uint64_t scan_blocks_max = 0;
     uint2 *d_dir_tab = nullptr;        // [max_events][L][n_phi] direct vote: per-bucket {lo, span}
     uint32_t *d_rk_info = nullptr;     // [rows][32] rank vote: J | unreachable << 31, then (0x80 + rank) x 0x01010101
-    uint32_t *d_rk_sorted = nullptr;   // [tiles][L][kRankSortStride] rank vote: sorted fine offsets
+    uint32_t *d_rk_sorted = nullptr;   // rank vote: [tiles][L][kRankSortStride] sorted fine offsets, then
+                                       // the whole-event tables (RankGlobLayout)
     size_t max_lds_direct = 65536;     // LDS budget of the direct vote's table staging
     size_t max_lds_rank = 65536;       // LDS budget of the rank vote (two workgroups per compute unit)
     uint64_t n_peak_tiles = 0;

@@ -96,6 +96,24 @@ __device__ __forceinline__ uint32_t rank_below(const uint32_t *s, uint32_t x)
     return lo;
 }
 
+// #{v < x} over all rows' sorted fine offsets of a layer, with the layout
+// of RankGlobLayout (header, 16-bit part counts, values): as rank_below.
+__device__ __forceinline__ uint32_t rank_all(const uint32_t *s, uint32_t x)
+{
+    const uint32_t f0 = s[0], f1 = s[1], sh = s[2], cnt = s[3];
+    if (cnt == 0 || x <= f0) return 0;
+    if (x > f1) return cnt;
+    const uint16_t *ix = reinterpret_cast<const uint16_t *>(s + 4);
+    const uint32_t *v = s + kRankGlobAt;
+    const uint32_t b = (x - f0) >> sh;
+    uint32_t lo = ix[b], hi = ix[b + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (v[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 }  // namespace
 
 // Static per-row words of the rank tables: [0, 16) J | unreachable << 31 per
@@ -108,7 +126,9 @@ template <int G, int NL, bool ALLV, bool BOUNDS>
 __global__ void __launch_bounds__(kRankThreads)
 k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi, const uint64_t *__restrict__ offs,
             uint64_t n_hits, int vec, const uint2 *__restrict__ tab, const uint32_t *__restrict__ rk_info,
-            const uint32_t *__restrict__ rk_sorted, uint32_t L, uint32_t rows, uint32_t nphi, uint32_t log2phi,
+            const uint32_t *__restrict__ rk_sorted, const uint32_t *__restrict__ rk_glob,
+            const uint32_t *__restrict__ rk_cnt, uint32_t gstride, uint32_t cstride,
+            uint32_t L, uint32_t rows, uint32_t nphi, uint32_t log2phi,
             uint32_t shift, uint32_t n_tiles, uint32_t run_tiles, uint32_t runs_per_event,
             uint16_t *__restrict__ acc)
 {
@@ -127,20 +147,17 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
 
     // LDS.  Tile items (!BOUNDS): the byte tables, the tile's sorted
     // offsets, the list of (layer, bucket) entries that can be empty, its
-    // length.  Event items (BOUNDS): [bmin | bmax] (N = L * nphi entries
-    // each) while the bounds are found; then, over the same bytes, every
-    // entry's interval packed in 6 bytes (three uint16 arrays: low halves of
-    // lo and hi, then their high bytes), the byte tables and the sorted
-    // offsets -- 8 N + 536 L bytes where the list form took 12 N + 536 L
-    // (46 against 66 KB for ten layers of 512 bins: three workgroups per CU
-    // instead of two).
+    // length.  Event items (BOUNDS), over the same bytes in turn: [bmin |
+    // bmax] (N = L * nphi entries each) while the bounds are found; all
+    // rows' sorted offsets per layer while each entry's interval [lo, hi]
+    // is ranked against them; then those ranks, g(lo) | g(hi + 1) << 16 per
+    // entry, the byte tables and the tile's counts cnt -- 8 N bytes in all
+    // (40 KB for ten layers of 512 bins).
     const uint32_t N = L * nphi;
     uint32_t *bmin = lds, *bmax = lds + (BOUNDS ? N : 0);
-    uint16_t *p_lo = reinterpret_cast<uint16_t *>(lds);           // BOUNDS: [N] lo & 0xFFFF
-    uint16_t *p_hi = p_lo + N;                                    //         [N] hi & 0xFFFF
-    uint16_t *p_hb = p_hi + N;                                    //         [N] lo >> 16 | (hi >> 16) << 8
-    uint32_t *bytes = lds + (BOUNDS ? 3 * N / 2 : 0);             // [L][ngrp + 1] x {a word, span word}
-    uint32_t *srt = bytes + L * (ngrp + 1) * 2;                   // [L][kRankSortStride]
+    uint32_t *p_g = lds;                                          // BOUNDS: [N] global ranks
+    uint32_t *bytes = lds + (BOUNDS ? N : 0);                     // [L][ngrp + 1] x {a word, span word}
+    uint32_t *srt = bytes + L * (ngrp + 1) * 2;                   // [L][kRankSortStride] or [L][cstride]
     uint16_t *ivl = reinterpret_cast<uint16_t *>(srt + L * kRankSortStride);   // !BOUNDS: [N]
     uint32_t &n_ivl = *(srt + L * kRankSortStride + (N + 1) / 2);              // !BOUNDS: the list's length
     // BOUNDS: the entries i = t + k * kRankThreads (k < EPT) of this thread,
@@ -183,9 +200,12 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
     };
     // Once per item: every byte-table entry starts at (a, span) = (0, 0),
     // never empty, and only entries with an interval (about a fifth of the
-    // buckets of a dense layer) are ranked per tile: event items keep each
-    // thread's entries' intervals packed in LDS (read into registers first,
-    // as they overwrite the bounds), tile items list the entries.
+    // buckets of a dense layer) are ranked per tile.  Event items rank each
+    // such interval once against all rows, g(x) = #{F < x} over the layer's
+    // sorted offsets of every row, so that a tile's a = #{F in tile, F < lo}
+    // is cnt[g(lo)] (the tile's share of the first g values; equal values
+    // never straddle g) and b = cnt[g(hi + 1)]; tile items list the
+    // entries and search each tile's own sorted offsets.
     if (BOUNDS) {
         __syncthreads();                                 // every hit's bounds update done
         uint32_t lo_r[EPT], hi_r[EPT];
@@ -197,17 +217,26 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             if (i < N) interval(i, lo_r[k], hi_r[k]);
         }
         __syncthreads();                                 // every bound read before any is overwritten
+        {
+            const uint4 *src4 = reinterpret_cast<const uint4 *>(rk_glob);   // gstride: a multiple of 4
+            for (uint32_t i = t; i < L * gstride / 4; i += nt) lds4[i] = src4[i];
+        }
+        __syncthreads();
+        uint32_t g_r[EPT];
 #pragma unroll
         for (uint32_t k = 0; k < EPT; ++k) {
             const uint32_t i = t + k * kRankThreads;
-            if (i < N) {
-                const bool h = lo_r[k] <= hi_r[k];       // then both are below 2^24
-                has_bits |= h ? 1u << k : 0u;
-                p_lo[i] = uint16_t(lo_r[k]);
-                p_hi[i] = uint16_t(hi_r[k]);
-                p_hb[i] = h ? uint16_t((lo_r[k] >> 16) | ((hi_r[k] >> 16) << 8)) : uint16_t(0);
+            g_r[k] = 0;
+            if (i < N && lo_r[k] <= hi_r[k]) {
+                has_bits |= 1u << k;
+                const uint32_t *gl = lds + (i >> log2phi) * gstride;
+                g_r[k] = rank_all(gl, lo_r[k]) | (rank_all(gl, hi_r[k] + 1u) << 16);
             }
         }
+        __syncthreads();                                 // the sorted offsets are no longer read
+#pragma unroll
+        for (uint32_t k = 0; k < EPT; ++k)
+            if (has_bits & (1u << k)) p_g[t + k * kRankThreads] = g_r[k];
         for (uint32_t i = t; i < L * (ngrp + 1) * 2; i += nt) bytes[i] = 0u;
         __syncthreads();
     } else {
@@ -240,14 +269,16 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
     }
 
     uint16_t *eacc = acc + uint64_t(e) * rows * nphi;
-    // a tile's sorted offsets are loaded into registers one tile ahead (the
-    // loads are in flight while the previous tile is ranked and voted) and
-    // stored to LDS when that tile is done
-    constexpr uint32_t kSrtRegs = (16 * kRankSortStride + kRankThreads - 1) / kRankThreads;
-    const uint32_t n_srt = L * kRankSortStride;
+    // a tile's sorted offsets (event items: its counts) are loaded into
+    // registers one tile ahead (the loads are in flight while the previous
+    // tile is ranked and voted) and stored to LDS when that tile is done
+    constexpr uint32_t kSrtRegs =
+        BOUNDS ? (LMAX * (kRankEventRowsMax / 4 + 1) + kRankThreads - 1) / kRankThreads
+               : (16 * kRankSortStride + kRankThreads - 1) / kRankThreads;
+    const uint32_t n_srt = L * (BOUNDS ? cstride : kRankSortStride);
     uint32_t sp[kSrtRegs];
     auto srt_load = [&](uint32_t tl) {
-        const uint32_t *gs = rk_sorted + size_t(tl) * n_srt;
+        const uint32_t *gs = (BOUNDS ? rk_cnt : rk_sorted) + size_t(tl) * n_srt;
 #pragma unroll
         for (uint32_t k = 0; k < kSrtRegs; ++k) {
             const uint32_t i = t + k * kRankThreads;
@@ -266,11 +297,8 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
         __syncthreads();
         if (tile + 1 < tile_hi) srt_load(tile + 1);
         // (a, span) bytes of the entries with an interval for this tile
-        auto rank_entry = [&](uint32_t i, uint32_t lo, uint32_t hi) {
+        auto put_entry = [&](uint32_t i, uint32_t a, uint32_t sp) {
             const uint32_t l = i >> log2phi, j = i & (nphi - 1);
-            const uint32_t *sl = srt + l * kRankSortStride;
-            const uint32_t a = rank_below(sl, lo);
-            const uint32_t sp = rank_below(sl, hi + 1u) - a;
             uint8_t *bl = reinterpret_cast<uint8_t *>(bytes + l * (ngrp + 1) * 2);
             const uint32_t g = j >> 2, k = j & 3;
             bl[g * 8 + k] = uint8_t(a);
@@ -285,8 +313,10 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
             // takes as many steps as its busiest lane has entries)
             for (uint32_t bits = has_bits; bits; bits &= bits - 1u) {
                 const uint32_t i = t + uint32_t(__builtin_ctz(bits)) * kRankThreads;
-                const uint32_t hb = p_hb[i];
-                rank_entry(i, uint32_t(p_lo[i]) | ((hb & 0xFFu) << 16), uint32_t(p_hi[i]) | ((hb >> 8) << 16));
+                const uint32_t g = p_g[i];
+                const uint8_t *cn = reinterpret_cast<const uint8_t *>(srt + (i >> log2phi) * cstride);
+                const uint32_t a = cn[g & 0xFFFFu];
+                put_entry(i, a, uint32_t(cn[g >> 16]) - a);
             }
         } else {
             const uint32_t nl_ivl = n_ivl;
@@ -294,7 +324,9 @@ k_vote_rank(const uint8_t *__restrict__ layer, const uint32_t *__restrict__ phi,
                 const uint32_t i = ivl[q];
                 uint32_t lo, hi;
                 interval(i, lo, hi);
-                rank_entry(i, lo, hi);
+                const uint32_t *sl = srt + (i >> log2phi) * kRankSortStride;
+                const uint32_t a = rank_below(sl, lo);
+                put_entry(i, a, rank_below(sl, hi + 1u) - a);
             }
         }
         __syncthreads();
@@ -393,14 +425,16 @@ void launch_rank_g(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint
                    uint32_t runs, uint32_t n_items, size_t lds, uint16_t *acc, hipStream_t s)
 {
     const hough_grid_spec &g = c->spec;
+    const RankGlobLayout y = rank_glob_layout(c->rows, g.n_layers);
+    const uint32_t *glob = c->d_rk_sorted + y.glob_at, *cnt = c->d_rk_sorted + y.cnt_at;
     if (bounds)
         hipLaunchKernelGGL((k_vote_rank<G, NL, ALLV, true>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer,
                            h->phi, h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
-                           g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
+                           glob, cnt, y.gstride, y.cstride, g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
     else
         hipLaunchKernelGGL((k_vote_rank<G, NL, ALLV, false>), dim3(n_items), dim3(kRankThreads), lds, s, h->layer,
                            h->phi, h->event_offsets, h->n_hits, vec, c->d_dir_tab, c->d_rk_info, c->d_rk_sorted,
-                           g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
+                           glob, cnt, y.gstride, y.cstride, g.n_layers, c->rows, g.n_phi, c->log2_phi, c->shift, n_tiles, run, runs, acc);
 }
 
 template <int G>
@@ -420,9 +454,12 @@ void launch_rank(hough_ctx *c, bool bounds, const hough_hits *h, int vec, uint32
 size_t rank_lds_bytes(const hough_ctx *c, bool bounds)
 {
     const size_t L = c->spec.n_layers, nphi = c->spec.n_phi, N = L * nphi;
-    const size_t tables = L * (nphi / 4 + 1) * 8 + L * kRankSortStride * 4;
-    if (bounds) return std::max(8 * N, 6 * N + tables);       // the bounds, then the packed intervals and tables
-    return tables + ((N + 1) / 2) * 4 + 4;
+    if (bounds) {
+        // the bounds; all rows' sorted offsets; the ranks, byte tables and counts
+        const RankGlobLayout y = rank_glob_layout(c->rows, uint32_t(L));
+        return 4 * std::max({2 * N, L * y.gstride, N + L * (nphi / 4 + 1) * 2 + L * y.cstride});
+    }
+    return L * (nphi / 4 + 1) * 8 + L * kRankSortStride * 4 + ((N + 1) / 2) * 4 + 4;
 }
 
 }  // namespace
@@ -438,8 +475,9 @@ void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, 
     const uint32_t L = g.n_layers;
     const uint32_t wmask = (1u << shift) - 1u;
     const uint32_t n_tiles = (rows + kRankTileRows - 1) / kRankTileRows;
+    const RankGlobLayout y = rank_glob_layout(rows, L);
     info.assign(size_t(rows) * 32, 0u);
-    sorted.assign(size_t(n_tiles) * L * kRankSortStride, 0xFFFFFFFFu);
+    sorted.assign(y.size, 0xFFFFFFFFu);
     std::vector<uint32_t> f;
     for (uint32_t t = 0; t < n_tiles; ++t) {
         const uint32_t r0 = t * kRankTileRows, r1 = std::min(rows, r0 + kRankTileRows);
@@ -473,6 +511,40 @@ void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, 
             }
         }
     }
+    if (y.size == y.glob_at) return;                 // too many rows for whole-event items
+    // per layer, every row's fine offset sorted with its tile, the search
+    // index (see rank_all), and per tile the counts cnt[k] of its rows among
+    // the first k sorted values
+    std::vector<std::pair<uint32_t, uint32_t>> fa(rows);
+    for (uint32_t l = 0; l < L; ++l) {
+        for (uint32_t r = 0; r < rows; ++r) fa[r] = {O[size_t(l) * rows + r] & wmask, r / kRankTileRows};
+        std::sort(fa.begin(), fa.end());
+        uint32_t *gl = sorted.data() + y.glob_at + size_t(l) * y.gstride;
+        for (uint32_t k = 0; k < rows; ++k) gl[kRankGlobAt + k] = fa[k].first;
+        const uint32_t f0 = fa.front().first, f1 = fa.back().first;
+        uint32_t sh = 0;
+        while (((f1 - f0) >> sh) > 255u) ++sh;
+        gl[0] = f0;
+        gl[1] = f1;
+        gl[2] = sh;
+        gl[3] = rows;
+        uint16_t *ix = reinterpret_cast<uint16_t *>(gl + 4);
+        for (uint32_t b = 0; b <= 256; ++b) {
+            const uint64_t edge = uint64_t(f0) + (uint64_t(b) << sh);
+            uint32_t n = 0;
+            while (n < rows && uint64_t(fa[n].first) < edge) ++n;
+            ix[b] = uint16_t(n);
+        }
+        for (uint32_t t = 0; t < n_tiles; ++t) {
+            uint8_t *cn = reinterpret_cast<uint8_t *>(sorted.data() + y.cnt_at + (size_t(t) * L + l) * y.cstride);
+            std::fill(cn, cn + size_t(y.cstride) * 4, uint8_t(0));
+            uint32_t run = 0;
+            for (uint32_t k = 0; k < rows; ++k) {
+                run += fa[k].second == t ? 1u : 0u;
+                cn[k + 1] = uint8_t(run);
+            }
+        }
+    }
 }
 
 bool rank_vote_usable(const hough_ctx *c, const uint16_t *acc)
@@ -490,7 +562,7 @@ hipError_t launch_vote_rank(hough_ctx *c, const hough_hits *h, uint16_t *acc, hi
     // whole events per item (bounds found in the kernel) when there are
     // enough events to fill the device and the bounds fit in LDS; else one
     // tile per item with the bounds from k_vote_bounds' table
-    const bool fits = rank_lds_bytes(c, true) <= c->max_lds_rank;
+    const bool fits = c->rows <= kRankEventRowsMax && rank_lds_bytes(c, true) <= c->max_lds_rank;
     const bool bounds = c->tun.vote_items == 1 ? fits : c->tun.vote_items == 2 ? false : uint64_t(E) >= want && fits;
     hipError_t err;
     KernelTimer t;
