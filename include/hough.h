@@ -177,8 +177,9 @@ typedef struct {
     uint32_t rz_slow_path;          /* 1 forces the global-memory histogram path of the rz vote */
     uint32_t rz_counter_bits;       /* rz LDS counter width: 0 = automatic, 4, 8 or 16 */
     uint32_t vote_items;            /* vote form 5: 0 = automatic, 1 = a whole event per workgroup (bucket
-                                       bounds found in LDS), 2 = one row tile per workgroup (bounds from a
-                                       table pass over the hits) */
+                                       bounds found in LDS; grids of at most 1024 rows whose tables fit in
+                                       LDS, else as 2), 2 = one row tile per workgroup (bounds from a table
+                                       pass over the hits) */
     uint32_t peak_algo;             /* peak search: 0 = default (2 where usable, else 1), 1 = tiles staged
                                        in LDS, 2 = row window in registers (n_d0 == 1, n_phi 256, 512 or
                                        1024, accumulator 16-byte aligned, 8 for n_phi 256) */
