@@ -181,8 +181,8 @@ typedef struct {
                                        LDS, else as 2), 2 = one row tile per workgroup (bounds from a table
                                        pass over the hits) */
     uint32_t peak_algo;             /* peak search: 0 = default (2 where usable, else 1), 1 = tiles staged
-                                       in LDS, 2 = row window in registers (n_d0 == 1, n_phi 256, 512 or
-                                       1024, accumulator 16-byte aligned, 8 for n_phi 256) */
+                                       in LDS, 2 = row window in registers (n_phi 256, 512 or 1024,
+                                       accumulator 16-byte aligned, 8 for n_phi 256) */
     uint32_t rz_member_cap;         /* rz: members a candidate may have on the fast path (a power of two,
                                        256 to 4096; more go to the exact path); 0 = 112 with 4-bit
                                        counters, else as many as fit the LDS budget (at most 2048) */

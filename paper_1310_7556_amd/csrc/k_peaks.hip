@@ -495,7 +495,7 @@ uint64_t peak_items(const hough_ctx *c, uint32_t n_events, const uint16_t *acc)
 {
     if (peak_rows_cells_per_lane(c, acc, n_events)) {
         const uint32_t R = peak_rows_strip(c);
-        return uint64_t(n_events) * ((c->spec.n_qpt + R - 1) / R);
+        return uint64_t(n_events) * c->spec.n_d0 * ((c->spec.n_qpt + R - 1) / R);
     }
     const bool vec = c->spec.n_phi >= 8 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0 &&
                      fit_rows(c, true) > 0;
@@ -527,7 +527,8 @@ hipError_t launch_peaks(hough_ctx *c, const uint16_t *acc, uint32_t n_events, ho
         err = launch_peaks_rows_pass(c, false, acc, n_events, peaks, capacity, ps, s);
         if (timed) prof_end(c, s, &t);
         if (err != hipSuccess) return err;
-        if ((err = launch_scan_counts(c, ps.tile_counts, uint64_t(n_events) * n_strips, ps.tile_off, n_strips,
+        if ((err = launch_scan_counts(c, ps.tile_counts, uint64_t(n_events) * c->spec.n_d0 * n_strips, ps.tile_off,
+                                      uint64_t(c->spec.n_d0) * n_strips,
                                       event_peak_offsets, s, ps.scan_part, ps.scan_off, ps.scan_blocks_max,
                                       timed)) != hipSuccess)
             return err;

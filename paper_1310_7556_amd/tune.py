@@ -37,7 +37,7 @@ def vote_space():
 
 
 def peak_space():
-    return ([dict(peak_algo=2, peak_rows=r) for r in (16, 32, 64, 128)] +
+    return ([dict(peak_algo=2, peak_rows=r) for r in (4, 8, 16, 32, 64, 128)] +
             [dict(peak_algo=1, peak_rows=r) for r in (2, 4, 8, 16, 32, 64)])
 
 

@@ -244,7 +244,10 @@ def test_rank_vote_form(H, kw, items):
 PEAK_SPECS = [dict(n_phi=256, n_qpt=16), dict(n_phi=512, n_qpt=300), dict(n_phi=1024, n_qpt=129),
               dict(n_phi=256, n_qpt=1), dict(n_phi=512, n_qpt=2, threshold=0),
               dict(n_phi=256, n_qpt=70, threshold=0), dict(n_phi=512, n_qpt=33, threshold=11),
-              dict(n_phi=1024, n_qpt=5, threshold=17)]
+              dict(n_phi=1024, n_qpt=5, threshold=17),
+              dict(n_phi=256, n_qpt=40, n_d0=5, d0_lo_mm=-120.0, d0_hi_mm=120.0),
+              dict(n_phi=512, n_qpt=33, n_d0=3, d0_lo_mm=-60.0, d0_hi_mm=60.0, threshold=0),
+              dict(n_phi=1024, n_qpt=17, n_d0=2, d0_lo_mm=-30.0, d0_hi_mm=30.0)]
 
 
 @pytest.mark.parametrize("kw", PEAK_SPECS)
@@ -252,10 +255,11 @@ PEAK_SPECS = [dict(n_phi=256, n_qpt=16), dict(n_phi=512, n_qpt=300), dict(n_phi=
                                     dict(peak_algo=2, peak_rows=3), dict(peak_algo=2, peak_rows=4096)])
 def test_peak_forms(H, kw, tuning):
     """The row-window peak form (a wavefront strip of rows in registers,
-    neighbours across lanes by wave rotates) and the LDS tile form against
-    the oracle: one-row and two-row grids, strips of 1, 3 and all rows
-    (ragged last strips), thresholds 0 (every plateau cell), 11 and 17 (no
-    peaks), on ragged events and the adversarial layer layouts."""
+    neighbours across lanes by wave rotates; with a d0 axis the same rows of
+    the planes on either side) and the LDS tile form against the oracle:
+    one-row and two-row grids, 2, 3 and 5 d0 planes, strips of 1, 3 and all
+    rows (ragged last strips), thresholds 0 (every plateau cell), 11 and 17
+    (no peaks), on ragged events and the adversarial layer layouts."""
     spec = small_spec(n_z0=0, n_cot=0, **kw)
     tab = oracle.Tables(spec)
     for batch in (ragged_batch(), gap_layout_batch(spec["n_phi"])):
