@@ -394,9 +394,9 @@ TRAFFIC_KERNELS = {
                        "c4_batch_4096"),
     "vote_rank_event": ("hough::k_vote_rank<2, 10, true, true>", "paper_1310_7556_amd/csrc/k_vote_rank.hip",
                         "c4_batch_4096"),
-    "peaks_count": ("hough::(anonymous namespace)::k_peaks_rows<8, false>",
+    "peaks_count": ("hough::(anonymous namespace)::k_peaks_rows<8, false, false>",
                     "paper_1310_7556_amd/csrc/k_peaks_rows.hip", "c4_batch_4096"),
-    "peaks_write": ("hough::(anonymous namespace)::k_peaks_rows<8, true>",
+    "peaks_write": ("hough::(anonymous namespace)::k_peaks_rows<8, true, false>",
                     "paper_1310_7556_amd/csrc/k_peaks_rows.hip", "c4_batch_4096"),
 }
 # SQ counters of the counter profiles: two passes of at most 8 SQ counters
