@@ -259,8 +259,10 @@ k_peaks_rows(const uint16_t *__restrict__ acc, uint32_t n_qpt, uint32_t n_d0, ui
             pcc[d] = pcn[d];
             lrc[d] = lrn[d];
             rawc[d] = raw[d];
-            nbp[d] = nbc[d];
-            nbc[d] = nbn[d];
+            if (D3) {
+                nbp[d] = nbc[d];
+                nbc[d] = nbn[d];
+            }
         }
     };
 
@@ -292,8 +294,10 @@ k_peaks_rows(const uint16_t *__restrict__ acc, uint32_t n_qpt, uint32_t n_d0, ui
                     pcc[d] = pcn[d];
                     lrc[d] = lrn[d];
                     rawc[d] = raw[d];
-                    nbp[d] = nbc[d];
-                    nbc[d] = nbn[d];
+                    if (D3) {
+                        nbp[d] = nbc[d];
+                        nbc[d] = nbn[d];
+                    }
                 }
             } else {
                 advance(raw, nbn, q);
