@@ -52,6 +52,40 @@ def test_noalloc_peaks_equal_peaks_on_two_calls():
         np.testing.assert_array_equal(H.peaks_numpy(pk, off, 0), opk.astype(H.PEAK_DTYPE))
 
 
+def test_noalloc_peaks_equal_peaks_with_a_d0_axis():
+    """The same comparison on a grid with a d0 axis (5 planes) under the
+    row-window form, whose tiles are (event, plane, strip)."""
+    import torch
+    from paper_1310_7556_amd import hough as H
+    spec = synth.grid_spec("c2_single_1ktrk_rz")
+    spec.update(n_qpt=40, n_phi=256, n_d0=5, d0_lo_mm=-120.0, d0_hi_mm=120.0, n_z0=0, n_cot=0)
+    evs = []
+    for e, n in enumerate([3000, 0, 9000, 57, 4000, 1]):
+        rng = np.random.default_rng(400 + e)
+        evs.append((rng.integers(0, 10, n).astype(np.uint8),
+                    rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32),
+                    rng.integers(-1_200_000, 1_200_000, n).astype(np.int32)))
+    big = synth.concat_events(evs)
+    small = synth.concat_events(evs[2:4])
+    ctx = H.HoughContext(spec, max_events=big.n_events, max_hits=big.n_hits)
+    ctx.set_tuning(peak_algo=2, peak_rows=8)
+    tab = oracle.Tables(spec)
+    for batch in (big, small):
+        E = batch.n_events
+        print(f"noalloc d0 axis: {E} events", flush=True)
+        hits = H.DeviceHits.from_batch(batch)
+        acc = ctx.vote(hits)
+        cap = E * ctx.cells
+        ref_pk, ref_off = ctx.peaks(acc, E, capacity=cap)
+        pk, off = _noalloc(H, ctx, acc, E, cap)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(H.offsets_numpy(off), H.offsets_numpy(ref_off))
+        np.testing.assert_array_equal(H.peaks_numpy(pk, off), H.peaks_numpy(ref_pk, ref_off))
+        ev = batch.event(0)
+        _, opk, _ = oracle.run_event(tab, ev.layer, ev.phi, ev.z, with_rz=False)
+        np.testing.assert_array_equal(H.peaks_numpy(pk, off, 0), opk.astype(H.PEAK_DTYPE))
+
+
 def test_noalloc_peaks_refuses_more_tiles_than_its_scratch():
     import torch
     from paper_1310_7556_amd import hough as H
