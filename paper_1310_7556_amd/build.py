@@ -18,7 +18,7 @@ ARCH = "gfx950"
 
 HIP_SOURCES = ["api.hip", "k_util.hip", "k_bucket.hip", "k_vote.hip", "k_vote_gap.hip", "k_vote_direct.hip", "k_vote_rank.hip", "k_peaks.hip", "k_peaks_rows.hip", "k_rz.hip",
                "k_cluster.hip", "k_fit.hip"]
-CXX_SOURCES = ["tables.cpp"]
+CXX_SOURCES = ["tables.cpp", "rank_tables.cpp"]
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/hough.h"
+#include "rank_tables.h"
 #include "tables.h"
 
 // A kernel's dynamically sized LDS array (its byte size is given at launch).
@@ -26,42 +27,6 @@ constexpr uint32_t kMaxBucketBits = 12;
 // The offset table is followed by this many zero entries, so a kernel may
 // read a whole tile's worth of offsets past the last row.
 constexpr size_t kOPad = 64;
-
-// Rank form of the vote: rows per tile (ranks fit a byte), workgroup size
-// and the stride of a tile's sorted fine offsets per layer: 128 values +
-// padding, then a search index (kRankIndexAt: the smallest and largest
-// value, a shift, the count, and 257 byte counts of the values below each of
-// 256 equal parts of [smallest, largest]).
-constexpr uint32_t kRankTileRows = 128;
-constexpr uint32_t kRankThreads = 512;
-constexpr uint32_t kRankIndexAt = 132;
-constexpr uint32_t kRankSortStride = kRankIndexAt + 4 + 68;
-
-// Whole-event items rank each entry's interval once against all rows of its
-// layer.  Per layer, the fine offsets of every row sorted (from
-// kRankGlobAt), after a header (the smallest and largest value, a shift, the
-// count) and 257 16-bit counts of the values below each of 256 equal parts
-// of [smallest, largest]; per (tile, layer), the bytes cnt[k] = how many of
-// the first k sorted values belong to the tile, k = 0..rows.  Both follow
-// the per-tile tables in the same buffer; only grids of at most
-// kRankEventRowsMax rows have them.
-constexpr uint32_t kRankGlobAt = 4 + 129;
-constexpr uint32_t kRankEventRowsMax = 1024;
-struct RankGlobLayout {
-    size_t glob_at, cnt_at, size;   // in 32-bit words from the buffer's start
-    uint32_t gstride, cstride;      // per layer
-};
-inline RankGlobLayout rank_glob_layout(uint32_t rows, uint32_t L)
-{
-    RankGlobLayout y;
-    const size_t n_tiles = (rows + kRankTileRows - 1) / kRankTileRows;
-    y.gstride = (kRankGlobAt + rows + 3) & ~3u;
-    y.cstride = (rows + 1 + 3) / 4;
-    y.glob_at = n_tiles * L * kRankSortStride;
-    y.cnt_at = y.glob_at + size_t(L) * y.gstride;
-    y.size = rows <= kRankEventRowsMax ? y.cnt_at + n_tiles * L * y.cstride : y.glob_at;
-    return y;
-}
 
 struct KernelTimer {
     const char *name;
@@ -226,9 +191,6 @@ hipError_t launch_vote_direct(hough_ctx *c, const hough_hits *h, uint16_t *acc, 
 bool direct_vote_usable(const hough_ctx *c);
 hipError_t launch_vote_bounds(hough_ctx *c, const hough_hits *h, hipStream_t s);
 // rank form: spec support, host tables (built at create), usability, launch
-bool rank_vote_form(const hough_grid_spec &g);
-void build_rank_tables(const hough_grid_spec &g, uint32_t rows, uint32_t shift, const uint32_t *O, const uint8_t *V,
-                       std::vector<uint32_t> &info, std::vector<uint32_t> &sorted);
 bool rank_vote_usable(const hough_ctx *c, const uint16_t *acc);
 hipError_t launch_vote_rank(hough_ctx *c, const hough_hits *h, uint16_t *acc, hipStream_t s);
 uint32_t gap_rows(const hough_ctx *c);
